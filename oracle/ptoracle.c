@@ -1,0 +1,418 @@
+/* CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded reference for what the GPU rasterizer of
+ * Schuetz, Kerbl & Wimmer, "Software Rasterization of 2 Billion Points in
+ * Real Time" (HPG 2022) computes.  Only the test suite, the smoke check and
+ * the bench's CPU-baseline leg may load this library.  It shares no source,
+ * header, table or helper with the GPU library, and the GPU library never
+ * calls it.
+ *
+ * What is computed (the reading of the paper is spelled out per function):
+ *   O1 validate          -- every coordinate finite, n < 2^32.
+ *   O2 Morton order      -- Sec. 3.1 (group consecutive points, optionally
+ *                           sorted by Morton code / z-order).
+ *   O3 batches           -- Sec. 3.1 and Fig. "batches memory": fixed-size
+ *                           runs of consecutive points plus their bounding box.
+ *   O4 quantise + split  -- Sec. 3.3, Eq. 1 and the 10-bit packing listing.
+ *   O5 frame matrix      -- Sec. 3.2 point projection (toPixelID undefined in
+ *                           the paper: viewport folded into the matrix).
+ *   O6 per-batch prologue-- Sec. 3.2 (workgroup-wise frustum culling) and
+ *                           Sec. 3.3 (500-pixel precision rule).
+ *   O7 per-point raster  -- Sec. 3.2 point rasterization listing: project,
+ *                           64-bit key (depth bits << 32 | index), atomicMin.
+ *   O8 resolve           -- Sec. 3.3 visibility buffer: index -> colour.
+ *
+ * Arithmetic rules (both sides follow the same written definition):
+ *   - binary64 steps use plain + - * / with no fused multiply-add
+ *     (compiled with -ffp-contract=off), evaluated left to right;
+ *   - per-point projection is binary32 with explicit fmaf in a fixed order;
+ *   - the pixel is the exact floor of the real quotient hx/hw (computed as
+ *     floor of the binary64 quotient, which is exact: see or_render).
+ *
+ * Parity pins: tests/test_oracle_*.py (hand-placed example, exact-rational
+ * brute force, closed forms and invariants).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  uint32_t first, count;
+  float min[3], max[3];
+} or_batch; /* 32 bytes */
+
+typedef struct {
+  int precision; /* 0 adaptive, 10/20/30 forced */
+  int cull;      /* 1 = batch frustum culling */
+  float t10, t20;
+} or_opts;
+
+typedef struct {
+  int culled;
+  int level; /* 10, 20 or 30 */
+  float P[3][3];
+  float t[3];
+} or_decision;
+
+typedef struct {
+  uint64_t batches, culled, points;
+  uint64_t level_batches[3], level_points[3];
+} or_stats;
+
+#define OR_EMPTY 0xFFFFFFFFFFFFFFFFull
+
+static inline uint32_t f32_bits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return u;
+}
+
+/* ---------------------------------------------------------------- O1 */
+/* Returns -1 if every coordinate is finite, else the index of the first
+ * point with a non-finite coordinate. */
+int64_t or_validate(const float* xyz, uint64_t n) {
+  for (uint64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a)
+      if (!isfinite(xyz[3 * i + a])) return (int64_t)i;
+  return -1;
+}
+
+/* ---------------------------------------------------------------- O2 */
+/* Cloud bounding box (exact fp32 min / max). */
+void or_cloud_aabb(const float* xyz, uint64_t n, float mn[3], float mx[3]) {
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = INFINITY;
+    mx[a] = -INFINITY;
+  }
+  for (uint64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      float v = xyz[3 * i + a];
+      if (v < mn[a]) mn[a] = v;
+      if (v > mx[a]) mx[a] = v;
+    }
+}
+
+/* Morton code (Sec. 3.1 names z-order without defining it; reading):
+ * per axis q = min(floor(2^21 (x - cmin) / (cmax - cmin)), 2^21 - 1) in
+ * binary64 (q = 0 when the extent is 0); bit b of x, y, z goes to code bit
+ * 3b, 3b+1, 3b+2. */
+void or_morton_codes(const float* xyz, uint64_t n, const float mn[3], const float mx[3],
+                     uint64_t* codes) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      double d = (double)xyz[3 * i + a] - (double)mn[a];
+      double s = (double)mx[a] - (double)mn[a];
+      if (s == 0.0) {
+        q[a] = 0;
+      } else {
+        double f = floor((d * 2097152.0) / s);
+        q[a] = f > 2097151.0 ? 2097151u : (uint32_t)f;
+      }
+    }
+    uint64_t c = 0;
+    for (int b = 0; b < 21; ++b)
+      for (int a = 0; a < 3; ++a) c |= (uint64_t)((q[a] >> b) & 1u) << (3 * b + a);
+    codes[i] = c;
+  }
+}
+
+typedef struct {
+  uint64_t code;
+  uint64_t idx;
+} or_pair;
+static int cmp_pair(const void* a, const void* b) {
+  const or_pair* x = (const or_pair*)a;
+  const or_pair* y = (const or_pair*)b;
+  if (x->code != y->code) return x->code < y->code ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+/* Stable order by code: perm[sorted position] = original index.  Sorting the
+ * pairs (code, index) lexicographically is the same as a stable sort. */
+int or_morton_order(const uint64_t* codes, uint64_t n, uint32_t* perm) {
+  or_pair* p = (or_pair*)malloc(sizeof(or_pair) * (n ? n : 1));
+  if (!p) return -2;
+  for (uint64_t i = 0; i < n; ++i) {
+    p[i].code = codes[i];
+    p[i].idx = i;
+  }
+  qsort(p, n, sizeof(or_pair), cmp_pair);
+  for (uint64_t i = 0; i < n; ++i) perm[i] = (uint32_t)p[i].idx;
+  free(p);
+  return 0;
+}
+
+/* ---------------------------------------------------------------- O3 */
+/* Batch b holds points [b S, min((b+1) S, n)) and their fp32 bounding box
+ * (Sec. 3.1: first index, count, bounding box per batch). */
+uint64_t or_batch_count(uint64_t n, uint32_t S) { return (n + S - 1) / S; }
+
+void or_make_batches(const float* xyz, uint64_t n, uint32_t S, or_batch* out) {
+  uint64_t nb = or_batch_count(n, S);
+  for (uint64_t b = 0; b < nb; ++b) {
+    uint64_t lo = b * S, hi = lo + S < n ? lo + S : n;
+    or_batch* B = &out[b];
+    B->first = (uint32_t)lo;
+    B->count = (uint32_t)(hi - lo);
+    for (int a = 0; a < 3; ++a) {
+      B->min[a] = INFINITY;
+      B->max[a] = -INFINITY;
+    }
+    for (uint64_t i = lo; i < hi; ++i)
+      for (int a = 0; a < 3; ++a) {
+        float v = xyz[3 * i + a];
+        if (v < B->min[a]) B->min[a] = v;
+        if (v > B->max[a]) B->max[a] = v;
+      }
+  }
+}
+
+/* ---------------------------------------------------------------- O4 */
+/* Eq. 1: X30 = min(floor(2^30 (x - boxMin) / boxSize), 2^30 - 1), per axis,
+ * relative to the point's batch box, in binary64 with one correctly rounded
+ * division; 0 when boxSize is 0.  Split (Sec. 3.3): low = bits 29..20,
+ * medium = bits 19..10, high = bits 9..0, each packed x | y << 10 | z << 20
+ * as in the packing listing, bits 30-31 zero. */
+uint32_t or_eq1(float x, float bmin, float bmax) {
+  double d = (double)x - (double)bmin;
+  double s = (double)bmax - (double)bmin;
+  if (s == 0.0) return 0;
+  double f = floor((d * 1073741824.0) / s);
+  return f > 1073741823.0 ? 1073741823u : (uint32_t)f;
+}
+
+void or_quantize(const float* xyz, const or_batch* batches, uint64_t nb, uint32_t* low,
+                 uint32_t* med, uint32_t* high) {
+  for (uint64_t b = 0; b < nb; ++b) {
+    const or_batch* B = &batches[b];
+    for (uint64_t i = B->first; i < (uint64_t)B->first + B->count; ++i) {
+      uint32_t lw = 0, mw = 0, hw = 0;
+      for (int a = 0; a < 3; ++a) {
+        uint32_t X30 = or_eq1(xyz[3 * i + a], B->min[a], B->max[a]);
+        lw |= ((X30 >> 20) & 1023u) << (10 * a);
+        mw |= ((X30 >> 10) & 1023u) << (10 * a);
+        hw |= (X30 & 1023u) << (10 * a);
+      }
+      low[i] = lw;
+      med[i] = mw;
+      high[i] = hw;
+    }
+  }
+}
+
+/* Whole load-time build: optional Morton order, batches, Eq. 1 split.
+ * Outputs are in render order; perm[render index] = input index. */
+int or_build(const float* xyz, const uint32_t* rgba, uint64_t n, uint32_t S, int morton,
+             float* xyz_out, uint32_t* colors, uint32_t* perm, or_batch* batches, uint32_t* low,
+             uint32_t* med, uint32_t* high) {
+  if (n >= 0xFFFFFFFFull || S == 0) return -1;
+  if (or_validate(xyz, n) >= 0) return -5;
+  if (morton) {
+    float mn[3], mx[3];
+    or_cloud_aabb(xyz, n, mn, mx);
+    uint64_t* codes = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+    if (!codes) return -2;
+    or_morton_codes(xyz, n, mn, mx, codes);
+    int rc = or_morton_order(codes, n, perm);
+    free(codes);
+    if (rc) return rc;
+  } else {
+    for (uint64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    uint32_t s = perm[i];
+    xyz_out[3 * i] = xyz[3 * s];
+    xyz_out[3 * i + 1] = xyz[3 * s + 1];
+    xyz_out[3 * i + 2] = xyz[3 * s + 2];
+    colors[i] = rgba[s];
+  }
+  uint64_t nb = or_batch_count(n, S);
+  or_make_batches(xyz_out, n, S, batches);
+  or_quantize(xyz_out, batches, nb, low, med, high);
+  return 0;
+}
+
+/* ---------------------------------------------------------------- O5 */
+/* Pixel-space matrix.  view and proj: row-major storage, column vectors
+ * (clip = proj * view * [x y z 1]^T), OpenGL clip space.  Window x =
+ * (x_clip / w_clip + 1) W / 2, so hx = (W/2)(row0 + row3) . p, hy likewise
+ * with H, and hw = row3 . p; rows of Pm: 0 -> hx, 1 -> hy, 2 -> hw.
+ * binary64, no FMA, sums left to right. */
+void or_frame_matrix(const float view[16], const float proj[16], uint32_t w, uint32_t h,
+                     double Pm[3][4]) {
+  double C[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      C[i][j] = (((double)proj[4 * i + 0] * (double)view[0 + j] +
+                  (double)proj[4 * i + 1] * (double)view[4 + j]) +
+                 (double)proj[4 * i + 2] * (double)view[8 + j]) +
+                (double)proj[4 * i + 3] * (double)view[12 + j];
+  for (int j = 0; j < 4; ++j) {
+    Pm[0][j] = (0.5 * (double)w) * (C[0][j] + C[3][j]);
+    Pm[1][j] = (0.5 * (double)h) * (C[1][j] + C[3][j]);
+    Pm[2][j] = C[3][j];
+  }
+}
+
+/* ---------------------------------------------------------------- O6 */
+/* Per-batch prologue (Sec. 3.2 culling, Sec. 3.3 precision choice).
+ *  corners: the 8 corners of [min, max]; per corner and row r:
+ *      h_r = ((Pm[r][0] cx + Pm[r][1] cy) + Pm[r][2] cz) + Pm[r][3]
+ *      a_r = ((|Pm[r][0] cx| + |Pm[r][1] cy|) + |Pm[r][2] cz|) + |Pm[r][3]|
+ *  margin M_r = 2^-16 max over corners of a_r (covers every rounding of the
+ *      fp32 per-point evaluation, which is below 2^-20 a_r);
+ *  cull (conservative) iff for one plane all 8 corners are outside by the
+ *      margin: hw < -Mw; hx < -Mx; hx - W hw > Mx + W Mw; hy < -My;
+ *      hy - H hw > My + H Mw.  Near/far planes are not tested.
+ *  level: E = +inf if any corner has hw <= 0, else the larger side of the
+ *      screen-space box of the projected corners (correctly rounded binary64
+ *      divisions); k = 10 if E < t10 (500 px), 20 if E < t20, else 30.
+ *  fold (lower-corner decode: unknown low bits are zero, so a point decodes
+ *      to min + F size 2^-k):  P[r][j] = fp32(Pm[r][j] (size_j 2^-k)),
+ *      t[r] = fp32(((Pm[r][0] min_x + Pm[r][1] min_y) + Pm[r][2] min_z) + Pm[r][3]). */
+void or_decide(const double Pm[3][4], const or_batch* B, uint32_t w, uint32_t h,
+               const or_opts* o, or_decision* d) {
+  double s[3];
+  for (int a = 0; a < 3; ++a) s[a] = (double)B->max[a] - (double)B->min[a];
+  double H[3][8], M[3];
+  for (int r = 0; r < 3; ++r) {
+    double amax = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      double cx = (double)((c & 1) ? B->max[0] : B->min[0]);
+      double cy = (double)((c & 2) ? B->max[1] : B->min[1]);
+      double cz = (double)((c & 4) ? B->max[2] : B->min[2]);
+      H[r][c] = ((Pm[r][0] * cx + Pm[r][1] * cy) + Pm[r][2] * cz) + Pm[r][3];
+      double a = ((fabs(Pm[r][0] * cx) + fabs(Pm[r][1] * cy)) + fabs(Pm[r][2] * cz)) + fabs(Pm[r][3]);
+      if (a > amax) amax = a;
+    }
+    M[r] = 0x1p-16 * amax;
+  }
+  double Wd = (double)w, Hd = (double)h;
+  int behind = 1, left = 1, right = 1, bottom = 1, top = 1;
+  for (int c = 0; c < 8; ++c) {
+    if (!(H[2][c] < -M[2])) behind = 0;
+    if (!(H[0][c] < -M[0])) left = 0;
+    if (!(H[0][c] - Wd * H[2][c] > M[0] + Wd * M[2])) right = 0;
+    if (!(H[1][c] < -M[1])) bottom = 0;
+    if (!(H[1][c] - Hd * H[2][c] > M[1] + Hd * M[2])) top = 0;
+  }
+  d->culled = o->cull ? (behind | left | right | bottom | top) : 0;
+
+  int k;
+  if (o->precision == 10 || o->precision == 20 || o->precision == 30) {
+    k = o->precision;
+  } else {
+    int front = 1;
+    for (int c = 0; c < 8; ++c)
+      if (!(H[2][c] > 0.0)) front = 0;
+    double E = INFINITY;
+    if (front) {
+      double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+      for (int c = 0; c < 8; ++c) {
+        double u = H[0][c] / H[2][c], v = H[1][c] / H[2][c];
+        if (u < umin) umin = u;
+        if (u > umax) umax = u;
+        if (v < vmin) vmin = v;
+        if (v > vmax) vmax = v;
+      }
+      double ex = umax - umin, ey = vmax - vmin;
+      E = ex > ey ? ex : ey;
+    }
+    k = E < (double)o->t10 ? 10 : (E < (double)o->t20 ? 20 : 30);
+  }
+  d->level = k;
+  double scale = k == 10 ? 0x1p-10 : (k == 20 ? 0x1p-20 : 0x1p-30);
+  for (int r = 0; r < 3; ++r) {
+    for (int j = 0; j < 3; ++j) d->P[r][j] = (float)(Pm[r][j] * (s[j] * scale));
+    d->t[r] = (float)(((Pm[r][0] * (double)B->min[0] + Pm[r][1] * (double)B->min[1]) +
+                       Pm[r][2] * (double)B->min[2]) +
+                      Pm[r][3]);
+  }
+}
+
+/* ---------------------------------------------------------------- O7 */
+/* Render every non-culled batch into vb (w*h entries, row 0 = bottom).
+ * vb must be filled with OR_EMPTY by the caller (or hold a previous partial
+ * result: the operation is a running minimum).
+ *  decode: F = low field (k=10); (low << 10) | med (k=20);
+ *          (low << 20) | (med << 10) | high (k=30); X = (float)F (RNE).
+ *  project: hx = fmaf(P02, Z, fmaf(P01, Y, fmaf(P00, X, t0))), same for hy, hw.
+ *  keep iff hw > 0 and 0 <= hx < W hw and 0 <= hy < H hw (exact in binary64:
+ *      W hw has at most 37 significant bits).
+ *  pixel: px = floor(hx / hw) exactly.  floor of the binary64 quotient is
+ *      exact here: for binary32 hx, hw with 0 <= q = hx/hw < 2^13, a
+ *      non-integer q is at least 2^-25 away from every integer while the
+ *      binary64 quotient is within 2^-40 of q, and an integer q is exact.
+ *  key: (float bits of hw) << 32 | point index (Sec. 3.2 listing; hw > 0,
+ *      so the bits order like the values); vb[p] = min(vb[p], key).
+ * If batch_ids is non-NULL only those batches are rendered (any order). */
+void or_render(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, uint64_t nids,
+               const uint32_t* low, const uint32_t* med, const uint32_t* high, const float view[16],
+               const float proj[16], uint32_t w, uint32_t h, const or_opts* o, uint64_t* vb,
+               or_stats* st) {
+  double Pm[3][4];
+  or_frame_matrix(view, proj, w, h, Pm);
+  double Wd = (double)w, Hd = (double)h;
+  uint64_t n_iter = batch_ids ? nids : nb;
+  if (st) memset(st, 0, sizeof *st);
+  for (uint64_t it = 0; it < n_iter; ++it) {
+    uint64_t b = batch_ids ? batch_ids[it] : it;
+    const or_batch* B = &batches[b];
+    or_decision d;
+    or_decide(Pm, B, w, h, o, &d);
+    if (st) st->batches++;
+    if (d.culled) {
+      if (st) st->culled++;
+      continue;
+    }
+    int li = d.level / 10 - 1;
+    if (st) {
+      st->points += B->count;
+      st->level_batches[li]++;
+      st->level_points[li] += B->count;
+    }
+    for (uint64_t i = B->first; i < (uint64_t)B->first + B->count; ++i) {
+      float XYZ[3];
+      for (int a = 0; a < 3; ++a) {
+        uint32_t lo = (low[i] >> (10 * a)) & 1023u;
+        uint32_t F;
+        if (d.level == 10) {
+          F = lo;
+        } else if (d.level == 20) {
+          F = (lo << 10) | ((med[i] >> (10 * a)) & 1023u);
+        } else {
+          F = (lo << 20) | (((med[i] >> (10 * a)) & 1023u) << 10) | ((high[i] >> (10 * a)) & 1023u);
+        }
+        XYZ[a] = (float)F;
+      }
+      float hx = fmaf(d.P[0][2], XYZ[2], fmaf(d.P[0][1], XYZ[1], fmaf(d.P[0][0], XYZ[0], d.t[0])));
+      float hy = fmaf(d.P[1][2], XYZ[2], fmaf(d.P[1][1], XYZ[1], fmaf(d.P[1][0], XYZ[0], d.t[1])));
+      float hw = fmaf(d.P[2][2], XYZ[2], fmaf(d.P[2][1], XYZ[1], fmaf(d.P[2][0], XYZ[0], d.t[2])));
+      if (!(hw > 0.0f)) continue;
+      double dx = (double)hx, dy = (double)hy, dw = (double)hw;
+      if (!(dx >= 0.0 && dx < Wd * dw && dy >= 0.0 && dy < Hd * dw)) continue;
+      uint64_t px = (uint64_t)floor(dx / dw), py = (uint64_t)floor(dy / dw);
+      uint64_t key = ((uint64_t)f32_bits(hw) << 32) | (uint64_t)i;
+      uint64_t p = py * w + px;
+      if (key < vb[p]) vb[p] = key;
+    }
+  }
+}
+
+/* Per-batch decisions only (for counters and sampled checks). */
+void or_decide_all(const or_batch* batches, uint64_t nb, const float view[16], const float proj[16],
+                   uint32_t w, uint32_t h, const or_opts* o, or_decision* out) {
+  double Pm[3][4];
+  or_frame_matrix(view, proj, w, h, Pm);
+  for (uint64_t b = 0; b < nb; ++b) or_decide(Pm, &batches[b], w, h, o, &out[b]);
+}
+
+/* ---------------------------------------------------------------- O8 */
+/* Visibility-buffer resolve (Sec. 3.3): the colour of the winning point, or
+ * the clear colour where no point landed. */
+void or_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint32_t clear_rgba,
+                uint32_t* fb) {
+  for (uint64_t p = 0; p < npix; ++p)
+    fb[p] = vb[p] == OR_EMPTY ? clear_rgba : colors[(uint32_t)(vb[p] & 0xFFFFFFFFull)];
+}
