@@ -68,6 +68,14 @@ static inline uint32_t f32_bits(float f) {
   return u;
 }
 
+/* Order used for bounding boxes: IEEE 754 totalOrder restricted to finite
+ * values, i.e. the usual order with -0 below +0.  (The paper does not say
+ * which zero a box takes when both occur; a fixed total order makes the box
+ * independent of the order in which points are visited.) */
+static inline int f32_less(float a, float b) {
+  return a < b || (a == b && signbit(a) && !signbit(b));
+}
+
 /* ---------------------------------------------------------------- O1 */
 /* Returns -1 if every coordinate is finite, else the index of the first
  * point with a non-finite coordinate. */
@@ -79,7 +87,7 @@ int64_t or_validate(const float* xyz, uint64_t n) {
 }
 
 /* ---------------------------------------------------------------- O2 */
-/* Cloud bounding box (exact fp32 min / max). */
+/* Cloud bounding box (exact fp32 min / max in the order of f32_less). */
 void or_cloud_aabb(const float* xyz, uint64_t n, float mn[3], float mx[3]) {
   for (int a = 0; a < 3; ++a) {
     mn[a] = INFINITY;
@@ -88,8 +96,8 @@ void or_cloud_aabb(const float* xyz, uint64_t n, float mn[3], float mx[3]) {
   for (uint64_t i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) {
       float v = xyz[3 * i + a];
-      if (v < mn[a]) mn[a] = v;
-      if (v > mx[a]) mx[a] = v;
+      if (f32_less(v, mn[a])) mn[a] = v;
+      if (f32_less(mx[a], v)) mx[a] = v;
     }
 }
 
@@ -145,7 +153,8 @@ int or_morton_order(const uint64_t* codes, uint64_t n, uint32_t* perm) {
 
 /* ---------------------------------------------------------------- O3 */
 /* Batch b holds points [b S, min((b+1) S, n)) and their fp32 bounding box
- * (Sec. 3.1: first index, count, bounding box per batch). */
+ * (Sec. 3.1: first index, count, bounding box per batch), min and max in the
+ * order of f32_less. */
 uint64_t or_batch_count(uint64_t n, uint32_t S) { return (n + S - 1) / S; }
 
 void or_make_batches(const float* xyz, uint64_t n, uint32_t S, or_batch* out) {
@@ -162,8 +171,8 @@ void or_make_batches(const float* xyz, uint64_t n, uint32_t S, or_batch* out) {
     for (uint64_t i = lo; i < hi; ++i)
       for (int a = 0; a < 3; ++a) {
         float v = xyz[3 * i + a];
-        if (v < B->min[a]) B->min[a] = v;
-        if (v > B->max[a]) B->max[a] = v;
+        if (f32_less(v, B->min[a])) B->min[a] = v;
+        if (f32_less(B->max[a], v)) B->max[a] = v;
       }
   }
 }

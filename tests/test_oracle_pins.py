@@ -390,3 +390,16 @@ def test_validate_rejects_non_finite():
         assert oracle.validate(x) == 617
         with pytest.raises(ValueError):
             oracle.build_cloud(x, rgba, 64)
+
+
+def test_signed_zero_boxes_use_total_order():
+    """-0 sorts below +0 in every box, whichever order the points come in."""
+    for pts in ([[0.0, -0.0, 1.0], [-0.0, 0.0, 1.0]], [[-0.0, 0.0, 1.0], [0.0, -0.0, 1.0]]):
+        xyz = np.array(pts, np.float32)
+        B = oracle.build_cloud(xyz, np.zeros(2, np.uint32), 4, morton=False)
+        mn = B.batches["min"][0].view(np.uint32).tolist()
+        mx = B.batches["max"][0].view(np.uint32).tolist()
+        assert mn[:2] == [0x80000000, 0x80000000] and mx[:2] == [0, 0]
+        cmn, cmx = oracle.cloud_aabb(xyz)
+        assert cmn.view(np.uint32).tolist()[:2] == [0x80000000] * 2
+        assert cmx.view(np.uint32).tolist()[:2] == [0, 0]
