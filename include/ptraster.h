@@ -1,0 +1,171 @@
+/* ptraster.h -- C ABI of the MI355X (gfx950) point rasterizer.
+ *
+ * Method: Schuetz, Kerbl & Wimmer, "Software Rasterization of 2 Billion
+ * Points in Real Time" (HPG 2022).  One-pixel points are grouped into batches
+ * of consecutive points with a bounding box (Sec. 3.1); each GPU workgroup
+ * frustum-culls its batch and chooses 10-, 20- or 30-bit coordinates relative
+ * to the batch box (Sec. 3.2, 3.3, Eq. 1); every visible point is written with
+ * a 64-bit atomic minimum of (depth bits << 32 | point index) into a
+ * visibility buffer (Sec. 3.2 rasterization listing), and a resolve pass maps
+ * indices to colours (Sec. 3.3, visibility buffer).
+ *
+ * Conventions for every call:
+ *   - Every call returns pr_status (0 = PR_OK, negative = error) and never
+ *     throws; pr_last_error() gives a message for the calling thread.
+ *   - Device work is enqueued on the context's HIP stream and is asynchronous
+ *     unless stated.  Argument errors are reported at once; faults and
+ *     non-finite input found on the device are reported by the next call
+ *     that synchronises (pr_build_batches, pr_get_stats, pr_sync).
+ *   - Ownership: the caller allocates and owns every device buffer (cloud
+ *     buffers sized by pr_cloud_sizes, visibility buffers, framebuffers).
+ *     The library allocates device memory only in pr_create (a few hundred
+ *     bytes of frame constants and counters); never on the render path.
+ *   - Layouts: visibility buffer (VB) = uint64_t[h*w], framebuffer (FB) =
+ *     uint32_t[h*w], both row-major with row 0 at the bottom (NDC y = -1):
+ *     pixel (px, py) is element py*w + px.  Colours are opaque 32-bit words
+ *     (RGBA8, R in the low byte).  view and proj are float[16], row-major
+ *     storage, column vectors: clip = proj * view * (x, y, z, 1)^T in OpenGL
+ *     clip space (w_clip = -z_eye for a perspective projection).
+ *   - Keys: VB[p] = (bits of the point's w_clip as float) << 32 | point index,
+ *     where the index is the point's position in render order (after the
+ *     optional Morton sort; perm[] maps it back to input order).  Empty
+ *     pixels hold PR_EMPTY.  Keys compare as unsigned 64-bit integers.
+ *   - Limits: n < 2^32; 1 <= w, h <= 8192; batch sizes are multiples of 4.
+ */
+#ifndef PTRASTER_H
+#define PTRASTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PR_OK = 0,
+  PR_EINVAL = -1,     /* null pointer, undersized buffer, bad option, wrong cloud state */
+  PR_ENOMEM = -2,     /* host allocation failed */
+  PR_EDEVICE = -3,    /* no usable GPU, or a HIP call / kernel failed */
+  PR_ESTATE = -4,     /* call out of order (e.g. render before build) */
+  PR_ENONFINITE = -5, /* NaN or Inf in coordinates or matrices */
+  PR_ERANGE = -6      /* size outside the limits above */
+} pr_status;
+
+#define PR_EMPTY 0xFFFFFFFFFFFFFFFFull
+
+enum { PR_ADAPTIVE = 0, PR_FORCE10 = 10, PR_FORCE20 = 20, PR_FORCE30 = 30 };
+
+typedef struct pr_ctx pr_ctx;     /* device ordinal, HIP stream, frame constants, counters */
+typedef struct pr_cloud pr_cloud; /* host handle with non-owning device pointers */
+
+/* Batch record (Sec. 3.1: first point, number of points, bounding box). 32 bytes. */
+typedef struct {
+  uint32_t first, count;
+  float min[3], max[3];
+} pr_batch;
+
+/* Byte sizes of the cloud buffers; see pr_cloud_bufs. */
+typedef struct {
+  uint64_t xyz, rgba, low, med, high, colors, perm, batches, scratch;
+} pr_sizes;
+
+/* Caller-allocated device buffers of one cloud (each 256-byte aligned).
+ *   xyz     float[n][3]   positions (AoS), filled by pr_load_points; after a
+ *                         Morton build they are in render order
+ *   rgba    uint32[n]     input colours, filled by pr_load_points
+ *   low     uint32[n]     Eq. 1 bits 29..20 per axis, packed x | y<<10 | z<<20
+ *   med     uint32[n]     bits 19..10, same packing
+ *   high    uint32[n]     bits 9..0, same packing
+ *   colors  uint32[n]     colours in render order
+ *   perm    uint32[n]     perm[render index] = input index
+ *   batches pr_batch[nb]  nb = ceil(n / batch_size)
+ *   scratch               load-time working memory (Morton sort)
+ * capacity must hold the sizes the caller allocated (normally the output of
+ * pr_cloud_sizes); pr_build_batches checks it and fails with PR_EINVAL if a
+ * buffer is too small for (n, batch_size, morton). */
+typedef struct {
+  void *xyz, *rgba, *low, *med, *high, *colors, *perm, *batches, *scratch;
+  pr_sizes capacity;
+} pr_cloud_bufs;
+
+/* Per-frame options; NULL means the defaults in brackets. */
+typedef struct {
+  int32_t precision; /* PR_ADAPTIVE [default] or PR_FORCE10/20/30 (Sec. 3.3)          */
+  int32_t cull;      /* 1 [default]: skip batches whose box misses the view (Sec. 3.2)  */
+  float t10;         /* adaptive: 10 bits if the projected box is < t10 px [500]         */
+  float t20;         /* adaptive: 20 bits if < t20 px [512000 = 500 * 2^10], else 30    */
+  int32_t counters;  /* 1: accumulate pr_stats for this frame (extra atomics) [0]       */
+} pr_render_opts;
+
+/* Frame counters (Table 2 definitions): processed batches = every batch,
+ * processed points = points in batches that were not culled; atomics = number
+ * of 64-bit atomic minimum calls issued, which depends on timing and is
+ * reported, never compared. */
+typedef struct {
+  uint64_t batches, culled, points;
+  uint64_t level_batches[3], level_points[3]; /* index 0, 1, 2 = 10, 20, 30 bits */
+  uint64_t atomics;
+} pr_stats;
+
+/* Message of the last failed call on this thread (never NULL). */
+const char* pr_last_error(void);
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  Allocates 4 KiB of device memory for
+ * frame constants and counters.  PR_EDEVICE if no GPU is usable. */
+pr_status pr_create(int device, void* hip_stream, pr_ctx** out);
+void pr_destroy(pr_ctx* ctx);
+
+/* Byte sizes of the cloud buffers for n points in batches of batch_size
+ * (multiple of 4), with or without the Morton sort (Sec. 3.1).  Pure host
+ * arithmetic; needs no GPU. */
+pr_status pr_cloud_sizes(uint64_t n, uint32_t batch_size, int morton, pr_sizes* out);
+
+/* Copy n positions (float[n][3]) and colours (uint32[n]) into bufs->xyz and
+ * bufs->rgba (skipped where source and destination coincide), from host
+ * memory (src_on_device = 0) or device memory (1).  Creates a host handle
+ * that keeps `bufs` (not owning it).  Sec. 3.1: the data structure is built
+ * while the data set is loaded. */
+pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, uint64_t n,
+                         int src_on_device, const pr_cloud_bufs* bufs, pr_cloud** out);
+
+/* Load-time build (Sec. 3.1, 3.3): checks every coordinate is finite;
+ * optionally sorts the points by 63-bit Morton code (21 bits per axis over the
+ * cloud box, x in the lowest bit; stable); groups batch_size consecutive points
+ * into batches with their fp32 bounding boxes; quantises every coordinate by
+ * Eq. 1 relative to its batch box and splits the 30 bits into low / med /
+ * high words.  Synchronises the stream once.  PR_ENONFINITE if any
+ * coordinate is NaN or Inf. */
+pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton);
+
+/* Render one view (Sec. 3.2, 3.3): clears visbuf (uint64[h*w], device) to
+ * PR_EMPTY, then every batch is culled or rendered at its precision level and
+ * every visible point is combined into visbuf by 64-bit atomic minimum.
+ * visbuf must be 16-byte aligned (PR_EINVAL otherwise).  Asynchronous.  PR_ENONFINITE for non-finite matrices, PR_ESTATE before
+ * pr_build_batches. */
+pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16],
+                    uint32_t w, uint32_t h, const pr_render_opts* opts, uint64_t* visbuf);
+
+/* Resolve (Sec. 3.3): rgba_out[p] = colors[VB[p] & 0xFFFFFFFF], or
+ * clear_rgba where VB[p] == PR_EMPTY (or holds an index >= n, which a buffer
+ * rendered from this cloud never does).  visbuf and rgba_out (uint32[h*w])
+ * are device memory, 16-byte aligned (PR_EINVAL otherwise).  Asynchronous. */
+pr_status pr_resolve(pr_ctx* ctx, const pr_cloud* cloud, const uint64_t* visbuf, uint32_t w,
+                     uint32_t h, uint32_t clear_rgba, uint32_t* rgba_out);
+
+/* Counters of the last pr_render that had counters = 1.  Synchronises. */
+pr_status pr_get_stats(pr_ctx* ctx, pr_stats* out);
+
+/* Wait for the context's stream; reports device-side failures. */
+pr_status pr_sync(pr_ctx* ctx);
+
+/* Cloud facts: point count, batch count, batch size (0 before a build). */
+pr_status pr_cloud_info(const pr_cloud* cloud, uint64_t* n, uint64_t* nbatches, uint32_t* batch_size);
+
+/* Free the host handle only; device buffers stay the caller's. */
+void pr_cloud_free(pr_cloud* cloud);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTRASTER_H */

@@ -75,7 +75,7 @@ def _lib_():
         L.or_decide_all.argtypes = [P, U64, P, P, U32, U32, ctypes.POINTER(Opts), P]
         L.or_render.argtypes = [P, U64, P, U64, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts), P,
                                 ctypes.POINTER(Stats)]
-        L.or_resolve.argtypes = [P, U64, P, U32, P]
+        L.or_resolve.argtypes = [P, U64, P, U64, U32, P]
         _lib = L
     return _lib
 
@@ -208,5 +208,5 @@ def resolve(vb, colors, clear_rgba: int = 0):
     vb = _c(vb, np.uint64)
     colors = _c(colors, np.uint32)
     fb = np.empty(vb.shape[0], np.uint32)
-    _lib_().or_resolve(_p(vb), vb.shape[0], _p(colors), clear_rgba, _p(fb))
+    _lib_().or_resolve(_p(vb), vb.shape[0], _p(colors), colors.shape[0], clear_rgba, _p(fb))
     return fb

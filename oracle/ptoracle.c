@@ -419,9 +419,13 @@ void or_decide_all(const or_batch* batches, uint64_t nb, const float view[16], c
 
 /* ---------------------------------------------------------------- O8 */
 /* Visibility-buffer resolve (Sec. 3.3): the colour of the winning point, or
- * the clear colour where no point landed. */
-void or_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint32_t clear_rgba,
-                uint32_t* fb) {
-  for (uint64_t p = 0; p < npix; ++p)
-    fb[p] = vb[p] == OR_EMPTY ? clear_rgba : colors[(uint32_t)(vb[p] & 0xFFFFFFFFull)];
+ * the clear colour where no point landed.  An index that is not a point of
+ * this cloud (a buffer rendered from another cloud) also gives the clear
+ * colour; a buffer rendered from this cloud never holds one. */
+void or_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint64_t ncolors,
+                uint32_t clear_rgba, uint32_t* fb) {
+  for (uint64_t p = 0; p < npix; ++p) {
+    uint32_t idx = (uint32_t)(vb[p] & 0xFFFFFFFFull);
+    fb[p] = (vb[p] == OR_EMPTY || idx >= ncolors) ? clear_rgba : colors[idx];
+  }
 }

@@ -1,0 +1,18 @@
+"""MI355X point rasterizer -- Python binding of libptraster.so.
+
+Brute-force compute rasterization of one-pixel points into a 64-bit
+visibility buffer (Schuetz, Kerbl & Wimmer, "Software Rasterization of 2
+Billion Points in Real Time", Sec. 3).  Every step runs in the HIP kernels of
+``libptraster.so`` (gfx950); this module only marshals arguments through the
+C ABI of ``include/ptraster.h`` with the same function names.  PyTorch is used
+for device memory and streams.
+
+Importing fails loudly if the library has not been built
+(``python paper_2204_01287_amd/build.py`` or ``__graft_entry__.build()``).
+"""
+from ._binding import (  # noqa: F401
+    PR_ADAPTIVE, PR_EMPTY, PR_FORCE10, PR_FORCE20, PR_FORCE30, PrError, Sizes, CloudBufs, RenderOpts, Stats,
+    LIB_PATH, lib, pr_last_error, pr_create, pr_destroy, pr_cloud_sizes, pr_load_points, pr_build_batches,
+    pr_render, pr_resolve, pr_get_stats, pr_sync, pr_cloud_info, pr_cloud_free, EXPORTED,
+    DeviceCloud, Context,
+)

@@ -1,0 +1,240 @@
+"""ctypes marshalling for libptraster.so (see include/ptraster.h for semantics)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptraster.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python {os.path.join(_HERE, 'build.py')}` "
+        "(there is no fallback implementation)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+PR_ADAPTIVE, PR_FORCE10, PR_FORCE20, PR_FORCE30 = 0, 10, 20, 30
+PR_EMPTY = 0xFFFFFFFFFFFFFFFF
+_STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "PR_ESTATE",
+           -5: "PR_ENONFINITE", -6: "PR_ERANGE"}
+
+EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_load_points", "pr_build_batches",
+            "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free"]
+
+
+class PrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+        super().__init__(f"{where}: {self.name}: {pr_last_error()}")
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("xyz", "rgba", "low", "med", "high", "colors", "perm", "batches", "scratch")]
+
+
+class CloudBufs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("xyz", "rgba", "low", "med", "high", "colors", "perm", "batches", "scratch")] + \
+               [("capacity", Sizes)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("cull", ctypes.c_int32), ("t10", ctypes.c_float),
+                ("t20", ctypes.c_float), ("counters", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, precision=PR_ADAPTIVE, cull=1, t10=500.0, t20=512000.0, counters=0):
+        return cls(precision, cull, t10, t20, counters)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("culled", ctypes.c_uint64), ("points", ctypes.c_uint64),
+                ("level_batches", ctypes.c_uint64 * 3), ("level_points", ctypes.c_uint64 * 3),
+                ("atomics", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {"batches": self.batches, "culled": self.culled, "points": self.points,
+                "level_batches": list(self.level_batches), "level_points": list(self.level_points),
+                "atomics": self.atomics}
+
+
+_P, _U64, _U32, _I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+lib.pr_last_error.restype = ctypes.c_char_p
+lib.pr_last_error.argtypes = []
+lib.pr_create.argtypes = [_I, _P, ctypes.POINTER(_P)]
+lib.pr_destroy.argtypes = [_P]
+lib.pr_destroy.restype = None
+lib.pr_cloud_sizes.argtypes = [_U64, _U32, _I, ctypes.POINTER(Sizes)]
+lib.pr_load_points.argtypes = [_P, _P, _P, _U64, _I, ctypes.POINTER(CloudBufs), ctypes.POINTER(_P)]
+lib.pr_build_batches.argtypes = [_P, _P, _U32, _I]
+lib.pr_render.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts), _P]
+lib.pr_resolve.argtypes = [_P, _P, _P, _U32, _U32, _U32, _P]
+lib.pr_get_stats.argtypes = [_P, ctypes.POINTER(Stats)]
+lib.pr_sync.argtypes = [_P]
+lib.pr_cloud_info.argtypes = [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U32)]
+lib.pr_cloud_free.argtypes = [_P]
+lib.pr_cloud_free.restype = None
+for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_render", "pr_resolve",
+           "pr_get_stats", "pr_sync", "pr_cloud_info"):
+    getattr(lib, _f).restype = ctypes.c_int
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise PrError(status, where)
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor or numpy array (or an int / None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _mat16(m):
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(16))
+    return a, a.ctypes.data
+
+
+def pr_last_error() -> str:
+    return lib.pr_last_error().decode()
+
+
+def pr_create(device: int = 0, stream=None):
+    """Returns an opaque context handle (int).  stream: a hipStream_t as int, or a torch stream."""
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    h = _P()
+    _check(lib.pr_create(device, stream, ctypes.byref(h)), "pr_create")
+    return h.value
+
+
+def pr_destroy(ctx):
+    lib.pr_destroy(ctx)
+
+
+def pr_cloud_sizes(n: int, batch_size: int, morton: bool) -> Sizes:
+    s = Sizes()
+    _check(lib.pr_cloud_sizes(n, batch_size, int(morton), ctypes.byref(s)), "pr_cloud_sizes")
+    return s
+
+
+def pr_load_points(ctx, xyz, rgba, n: int, src_on_device: bool, bufs: CloudBufs):
+    h = _P()
+    _check(lib.pr_load_points(ctx, _ptr(xyz), _ptr(rgba), n, int(src_on_device), ctypes.byref(bufs), ctypes.byref(h)),
+           "pr_load_points")
+    return h.value
+
+
+def pr_build_batches(ctx, cloud, batch_size: int, morton: bool):
+    _check(lib.pr_build_batches(ctx, cloud, batch_size, int(morton)), "pr_build_batches")
+
+
+def pr_render(ctx, cloud, view, proj, w: int, h: int, opts: RenderOpts | None, visbuf):
+    v, vp = _mat16(view)
+    p, pp = _mat16(proj)
+    _check(lib.pr_render(ctx, cloud, vp, pp, w, h, ctypes.byref(opts) if opts is not None else None, _ptr(visbuf)),
+           "pr_render")
+
+
+def pr_resolve(ctx, cloud, visbuf, w: int, h: int, clear_rgba: int, rgba_out):
+    _check(lib.pr_resolve(ctx, cloud, _ptr(visbuf), w, h, clear_rgba & 0xFFFFFFFF, _ptr(rgba_out)), "pr_resolve")
+
+
+def pr_get_stats(ctx) -> dict:
+    s = Stats()
+    _check(lib.pr_get_stats(ctx, ctypes.byref(s)), "pr_get_stats")
+    return s.as_dict()
+
+
+def pr_sync(ctx):
+    _check(lib.pr_sync(ctx), "pr_sync")
+
+
+def pr_cloud_info(cloud):
+    n, nb, bs = _U64(), _U64(), _U32()
+    _check(lib.pr_cloud_info(cloud, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(bs)), "pr_cloud_info")
+    return n.value, nb.value, bs.value
+
+
+def pr_cloud_free(cloud):
+    lib.pr_cloud_free(cloud)
+
+
+# ------------------------------------------------- torch-owned memory plumbing
+class Context:
+    """A pr_ctx bound to a torch device and stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.handle = pr_create(device, self.stream.cuda_stream)
+
+    def close(self):
+        if self.handle:
+            pr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceCloud:
+    """Cloud buffers allocated as torch tensors (sized by pr_cloud_sizes), loaded and built."""
+
+    FIELDS = ("xyz", "rgba", "low", "med", "high", "colors", "perm", "batches", "scratch")
+
+    def __init__(self, ctx: Context, xyz, rgba, batch_size: int = 10240, morton: bool = False):
+        import torch
+
+        n = int(xyz.shape[0])
+        self.ctx, self.n, self.batch_size, self.morton = ctx, n, batch_size, morton
+        self.sizes = pr_cloud_sizes(n, batch_size, morton)
+        dev = torch.device("cuda", ctx.device)
+        self.mem = {f: torch.empty(max(getattr(self.sizes, f), 256), dtype=torch.uint8, device=dev)
+                    for f in self.FIELDS}
+        self.bufs = CloudBufs(*[self.mem[f].data_ptr() for f in self.FIELDS], self.sizes)
+        on_dev = hasattr(xyz, "is_cuda") and xyz.is_cuda
+        if not on_dev:
+            xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+            rgba = np.ascontiguousarray(rgba, dtype=np.uint32)
+        self._src = (xyz, rgba)  # keep host sources alive until the copies are done
+        self.handle = pr_load_points(ctx.handle, xyz, rgba, n, on_dev, self.bufs)
+        pr_build_batches(ctx.handle, self.handle, batch_size, morton)
+        self._src = None
+        self.nb = pr_cloud_info(self.handle)[1]
+
+    def view(self, field: str, dtype, count: int):
+        """A typed torch view of one buffer (e.g. view('low', torch.int32, n))."""
+        import torch
+
+        t = self.mem[field]
+        esize = torch.empty(0, dtype=dtype).element_size()
+        return t[: count * esize].view(dtype)
+
+    def close(self):
+        if self.handle:
+            pr_cloud_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,80 @@
+// Internal declarations shared by the host runtime and the kernel files of
+// libptraster.so.  Not part of the ABI (see include/ptraster.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptr {
+
+struct BatchRec {  // identical layout to pr_batch
+  uint32_t first, count;
+  float mn[3], mx[3];
+};
+static_assert(sizeof(BatchRec) == 32, "batch record is 32 bytes");
+
+// Frame constants, written by the clear kernel and read by the render kernel:
+// the pixel-space matrix rows (hx, hy, hw) in binary64.
+struct FrameConst {
+  double Pm[3][4];
+};
+
+// Device-side context block (one per pr_ctx), 4 KiB.
+struct DevBlock {
+  FrameConst fc;          // 96 B
+  uint64_t pad0[4];       // keep stats on their own 128-B line
+  uint64_t stats[16];     // batches, culled, points, lvl_b[3], lvl_p[3], atomics
+  uint32_t flags[16];     // [0] non-finite coordinate seen
+};
+enum { ST_BATCHES = 0, ST_CULLED, ST_POINTS, ST_LB0, ST_LB1, ST_LB2, ST_LP0, ST_LP1, ST_LP2, ST_ATOMICS };
+
+struct ViewArgs {
+  float view[16], proj[16];
+};
+
+struct RenderArgs {
+  const uint32_t* low;
+  const uint32_t* med;
+  const uint32_t* high;
+  const BatchRec* batches;
+  uint64_t* vb;
+  const DevBlock* dev;
+  uint64_t* stats;
+  uint32_t nb, W, H;
+  int32_t precision, cull, counters;
+  float t10, t20;
+};
+
+// ---- render path (kern_render.hip)
+hipError_t launch_clear(uint64_t* vb, uint64_t npix, const ViewArgs& v, uint32_t W, uint32_t H,
+                        DevBlock* dev, int reset_stats, hipStream_t s);
+hipError_t launch_render(const RenderArgs& a, hipStream_t s);
+hipError_t launch_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint64_t ncolors,
+                          uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
+
+// ---- load-time build (kern_build.hip)
+struct SortScratch {
+  uint64_t* keys0;
+  uint64_t* keys1;
+  uint32_t* vals1;  // vals0 is the caller's perm buffer
+  uint32_t* hist;   // 256 * nblk
+  uint32_t* part;   // scan partial sums
+  float* xyz_sorted;
+  uint32_t* aabb;   // 6 ordered keys: min x,y,z then max x,y,z
+  uint64_t nblk, npart;
+};
+// Scratch layout for n points (morton = 1); returns total bytes.
+uint64_t sort_scratch_layout(uint64_t n, uint8_t* base, SortScratch* out);
+uint64_t small_scratch_bytes();
+
+hipError_t launch_finite_check(const float* xyz, uint64_t n, uint32_t* flag, hipStream_t s);
+hipError_t launch_iota(uint32_t* p, uint64_t n, hipStream_t s);
+hipError_t launch_morton_codes(const float* xyz, uint64_t n, uint32_t* aabb, uint64_t* keys, uint32_t* vals,
+                               hipStream_t s);
+hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, hipStream_t s);
+hipError_t launch_gather(const float* xyz, const uint32_t* rgba, const uint32_t* perm, uint64_t n, float* xyz_out,
+                         uint32_t* colors, hipStream_t s);
+hipError_t launch_batch_bbox(const float* xyz, uint64_t n, uint32_t S, uint64_t nb, BatchRec* out, hipStream_t s);
+hipError_t launch_quantize(const float* xyz, uint64_t n, uint32_t S, const BatchRec* batches, uint32_t* low,
+                           uint32_t* med, uint32_t* high, hipStream_t s);
+
+}  // namespace ptr

@@ -1,0 +1,323 @@
+// Host runtime of libptraster.so: the C ABI declared in include/ptraster.h.
+// Validates arguments, lays out caller-provided memory, and enqueues the
+// build / render / resolve kernels on the context's HIP stream.
+#include "../../include/ptraster.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+struct pr_ctx {
+  int device;
+  hipStream_t stream;
+  ptr::DevBlock* dev;  // frame constants, counters, flags (device memory)
+};
+
+struct pr_cloud {
+  pr_ctx* ctx;
+  uint64_t n;
+  uint64_t nb;
+  uint32_t batch_size;
+  int morton;
+  int built;
+  pr_cloud_bufs bufs;
+};
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+pr_status fail(pr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+pr_status fail(pr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+pr_status hip_fail(hipError_t e, const char* what) {
+  return fail(PR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)               \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr uint64_t kMaxPoints = 0xFFFFFFFFull;  // n < 2^32: the key holds a 32-bit index
+constexpr uint32_t kMaxDim = 8192;
+
+uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+pr_status check_dims(uint32_t w, uint32_t h) {
+  if (w < 1 || h < 1 || w > kMaxDim || h > kMaxDim)
+    return fail(PR_ERANGE, "image size %ux%u outside 1..%u", w, h, kMaxDim);
+  return PR_OK;
+}
+
+pr_status set_device(const pr_ctx* ctx) {
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  return PR_OK;
+}
+
+pr_status sizes_for(uint64_t n, uint32_t batch_size, int morton, pr_sizes* s) {
+  if (batch_size == 0 || (batch_size & 3u)) return fail(PR_EINVAL, "batch_size %u must be a positive multiple of 4", batch_size);
+  if (n > kMaxPoints - 1) return fail(PR_ERANGE, "n = %llu points: at most 2^32 - 1", (unsigned long long)n);
+  const uint64_t nb = (n + batch_size - 1) / batch_size;
+  s->xyz = a256(12 * n);
+  s->rgba = a256(4 * n);
+  s->low = s->med = s->high = s->colors = s->perm = a256(4 * n);
+  s->batches = a256(32 * nb);
+  s->scratch = a256(ptr::small_scratch_bytes() + (morton ? ptr::sort_scratch_layout(n, nullptr, nullptr) : 0));
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pr_last_error(void) { return g_err.c_str(); }
+
+pr_status pr_create(int device, void* hip_stream, pr_ctx** out) {
+  if (!out) return fail(PR_EINVAL, "pr_create: out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) return fail(PR_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+  if (device < 0 || device >= count) return fail(PR_EDEVICE, "device %d outside 0..%d", device, count - 1);
+  HIP_TRY(hipSetDevice(device), "hipSetDevice");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(PR_EDEVICE, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
+  pr_ctx* c = new (std::nothrow) pr_ctx;
+  if (!c) return fail(PR_ENOMEM, "pr_create: host allocation");
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->dev = nullptr;
+  e = hipMalloc(reinterpret_cast<void**>(&c->dev), 4096);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipMalloc(context block)");
+  }
+  e = hipMemsetAsync(c->dev, 0, 4096, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(c->dev);
+    delete c;
+    return hip_fail(e, "context block init");
+  }
+  *out = c;
+  return PR_OK;
+}
+
+void pr_destroy(pr_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(ctx->dev);
+  delete ctx;
+}
+
+pr_status pr_cloud_sizes(uint64_t n, uint32_t batch_size, int morton, pr_sizes* out) {
+  if (!out) return fail(PR_EINVAL, "pr_cloud_sizes: out is NULL");
+  return sizes_for(n, batch_size, morton, out);
+}
+
+pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, uint64_t n, int src_on_device,
+                         const pr_cloud_bufs* bufs, pr_cloud** out) {
+  if (!ctx || !bufs || !out) return fail(PR_EINVAL, "pr_load_points: NULL argument");
+  *out = nullptr;
+  if (n > kMaxPoints - 1) return fail(PR_ERANGE, "n = %llu points: at most 2^32 - 1", (unsigned long long)n);
+  if (n > 0 && (!xyz || !rgba || !bufs->xyz || !bufs->rgba)) return fail(PR_EINVAL, "pr_load_points: NULL buffer");
+  if (bufs->capacity.xyz < 12 * n || bufs->capacity.rgba < 4 * n)
+    return fail(PR_EINVAL, "pr_load_points: xyz/rgba buffers hold fewer than n points");
+  if (pr_status s = set_device(ctx)) return s;
+  const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (n > 0 && static_cast<const void*>(xyz) != bufs->xyz)
+    HIP_TRY(hipMemcpyAsync(bufs->xyz, xyz, 12 * n, kind, ctx->stream), "copy positions");
+  if (n > 0 && static_cast<const void*>(rgba) != bufs->rgba)
+    HIP_TRY(hipMemcpyAsync(bufs->rgba, rgba, 4 * n, kind, ctx->stream), "copy colours");
+  pr_cloud* c = new (std::nothrow) pr_cloud;
+  if (!c) return fail(PR_ENOMEM, "pr_load_points: host allocation");
+  c->ctx = ctx;
+  c->n = n;
+  c->nb = 0;
+  c->batch_size = 0;
+  c->morton = 0;
+  c->built = 0;
+  c->bufs = *bufs;
+  *out = c;
+  return PR_OK;
+}
+
+pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton) {
+  if (!ctx || !cloud) return fail(PR_EINVAL, "pr_build_batches: NULL argument");
+  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_build_batches: cloud belongs to another context");
+  pr_sizes need;
+  if (pr_status s = sizes_for(cloud->n, batch_size, morton, &need)) return s;
+  const pr_cloud_bufs& B = cloud->bufs;
+  const pr_sizes& cap = B.capacity;
+  if (cap.low < need.low || cap.med < need.med || cap.high < need.high || cap.colors < need.colors ||
+      cap.perm < need.perm || cap.batches < need.batches || cap.scratch < need.scratch)
+    return fail(PR_EINVAL, "pr_build_batches: a cloud buffer is smaller than pr_cloud_sizes requires");
+  const uint64_t n = cloud->n;
+  if (n > 0) {
+    const void* ptrs[] = {B.xyz, B.rgba, B.low, B.med, B.high, B.colors, B.perm, B.batches, B.scratch};
+    for (const void* p : ptrs)
+      if (!p) return fail(PR_EINVAL, "pr_build_batches: NULL cloud buffer");
+    for (const void* p : ptrs)
+      if (!aligned256(p)) return fail(PR_EINVAL, "pr_build_batches: cloud buffers must be 256-byte aligned");
+  }
+  if (pr_status s = set_device(ctx)) return s;
+  hipStream_t st = ctx->stream;
+  const uint64_t nb = (n + batch_size - 1) / batch_size;
+  cloud->built = 0;
+  uint32_t* flag = &ctx->dev->flags[0];
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(uint32_t), st), "clear flag");
+  if (n > 0) {
+    const float* xyz = static_cast<const float*>(B.xyz);
+    const uint32_t* rgba = static_cast<const uint32_t*>(B.rgba);
+    uint32_t* perm = static_cast<uint32_t*>(B.perm);
+    uint32_t* colors = static_cast<uint32_t*>(B.colors);
+    HIP_TRY(ptr::launch_finite_check(xyz, n, flag, st), "finite check");
+    const float* xyz_render = xyz;
+    if (morton) {
+      ptr::SortScratch sc;
+      uint8_t* base = static_cast<uint8_t*>(B.scratch) + ptr::small_scratch_bytes();
+      ptr::sort_scratch_layout(n, base, &sc);
+      HIP_TRY(ptr::launch_morton_codes(xyz, n, sc.aabb, sc.keys0, perm, st), "morton codes");
+      HIP_TRY(ptr::radix_sort_pairs(sc, perm, n, st), "radix sort");
+      HIP_TRY(ptr::launch_gather(xyz, rgba, perm, n, sc.xyz_sorted, colors, st), "gather");
+      xyz_render = sc.xyz_sorted;
+    } else {
+      HIP_TRY(ptr::launch_iota(perm, n, st), "iota");
+      HIP_TRY(hipMemcpyAsync(colors, rgba, 4 * n, hipMemcpyDeviceToDevice, st), "copy colours");
+    }
+    ptr::BatchRec* batches = static_cast<ptr::BatchRec*>(B.batches);
+    HIP_TRY(ptr::launch_batch_bbox(xyz_render, n, batch_size, nb, batches, st), "batch boxes");
+    HIP_TRY(ptr::launch_quantize(xyz_render, n, batch_size, batches, static_cast<uint32_t*>(B.low),
+                                 static_cast<uint32_t*>(B.med), static_cast<uint32_t*>(B.high), st),
+            "quantise");
+    if (morton) {  // leave the sorted positions in the caller's xyz buffer
+      ptr::SortScratch sc;
+      ptr::sort_scratch_layout(n, static_cast<uint8_t*>(B.scratch) + ptr::small_scratch_bytes(), &sc);
+      HIP_TRY(hipMemcpyAsync(B.xyz, sc.xyz_sorted, 12 * n, hipMemcpyDeviceToDevice, st), "sorted positions");
+    }
+  }
+  uint32_t h_flag = 0;
+  HIP_TRY(hipMemcpyAsync(&h_flag, flag, sizeof h_flag, hipMemcpyDeviceToHost, st), "read flag");
+  HIP_TRY(hipStreamSynchronize(st), "build");
+  if (h_flag) return fail(PR_ENONFINITE, "pr_build_batches: a coordinate is NaN or Inf");
+  cloud->nb = nb;
+  cloud->batch_size = batch_size;
+  cloud->morton = morton ? 1 : 0;
+  cloud->built = 1;
+  return PR_OK;
+}
+
+pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16], uint32_t w,
+                    uint32_t h, const pr_render_opts* opts, uint64_t* visbuf) {
+  if (!ctx || !cloud || !view || !proj || !visbuf) return fail(PR_EINVAL, "pr_render: NULL argument");
+  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_render: cloud belongs to another context");
+  if (!cloud->built) return fail(PR_ESTATE, "pr_render: cloud is not built (call pr_build_batches)");
+  if (pr_status s = check_dims(w, h)) return s;
+  if (reinterpret_cast<uintptr_t>(visbuf) & 15u) return fail(PR_EINVAL, "pr_render: visbuf must be 16-byte aligned");
+  pr_render_opts o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0};
+  if (opts) o = *opts;
+  if (o.precision != PR_ADAPTIVE && o.precision != PR_FORCE10 && o.precision != PR_FORCE20 &&
+      o.precision != PR_FORCE30)
+    return fail(PR_EINVAL, "pr_render: precision %d is not 0, 10, 20 or 30", o.precision);
+  if (std::isnan(o.t10) || std::isnan(o.t20)) return fail(PR_EINVAL, "pr_render: NaN threshold");
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(view[i]) || !std::isfinite(proj[i])) return fail(PR_ENONFINITE, "pr_render: non-finite matrix");
+  if (pr_status s = set_device(ctx)) return s;
+  ptr::ViewArgs va;
+  std::memcpy(va.view, view, sizeof va.view);
+  std::memcpy(va.proj, proj, sizeof va.proj);
+  const uint64_t npix = (uint64_t)w * h;
+  HIP_TRY(ptr::launch_clear(visbuf, npix, va, w, h, ctx->dev, o.counters ? 1 : 0, ctx->stream), "clear");
+  ptr::RenderArgs a;
+  a.low = static_cast<const uint32_t*>(cloud->bufs.low);
+  a.med = static_cast<const uint32_t*>(cloud->bufs.med);
+  a.high = static_cast<const uint32_t*>(cloud->bufs.high);
+  a.batches = static_cast<const ptr::BatchRec*>(cloud->bufs.batches);
+  a.vb = visbuf;
+  a.dev = ctx->dev;
+  a.stats = ctx->dev->stats;
+  a.nb = (uint32_t)cloud->nb;
+  a.W = w;
+  a.H = h;
+  a.precision = o.precision;
+  a.cull = o.cull ? 1 : 0;
+  a.counters = o.counters ? 1 : 0;
+  a.t10 = o.t10;
+  a.t20 = o.t20;
+  HIP_TRY(ptr::launch_render(a, ctx->stream), "render");
+  return PR_OK;
+}
+
+pr_status pr_resolve(pr_ctx* ctx, const pr_cloud* cloud, const uint64_t* visbuf, uint32_t w, uint32_t h,
+                     uint32_t clear_rgba, uint32_t* rgba_out) {
+  if (!ctx || !cloud || !visbuf || !rgba_out) return fail(PR_EINVAL, "pr_resolve: NULL argument");
+  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_resolve: cloud belongs to another context");
+  if (!cloud->built) return fail(PR_ESTATE, "pr_resolve: cloud is not built");
+  if (pr_status s = check_dims(w, h)) return s;
+  if (pr_status s = set_device(ctx)) return s;
+  if ((reinterpret_cast<uintptr_t>(visbuf) & 15u) || (reinterpret_cast<uintptr_t>(rgba_out) & 15u))
+    return fail(PR_EINVAL, "pr_resolve: visbuf and rgba_out must be 16-byte aligned");
+  HIP_TRY(ptr::launch_resolve(visbuf, (uint64_t)w * h, static_cast<const uint32_t*>(cloud->bufs.colors), cloud->n,
+                              clear_rgba, rgba_out, ctx->stream),
+          "resolve");
+  return PR_OK;
+}
+
+pr_status pr_get_stats(pr_ctx* ctx, pr_stats* out) {
+  if (!ctx || !out) return fail(PR_EINVAL, "pr_get_stats: NULL argument");
+  if (pr_status s = set_device(ctx)) return s;
+  uint64_t st[16];
+  HIP_TRY(hipMemcpyAsync(st, ctx->dev->stats, sizeof st, hipMemcpyDeviceToHost, ctx->stream), "read counters");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "pr_get_stats");
+  out->batches = st[ptr::ST_BATCHES];
+  out->culled = st[ptr::ST_CULLED];
+  out->points = st[ptr::ST_POINTS];
+  for (int i = 0; i < 3; ++i) {
+    out->level_batches[i] = st[ptr::ST_LB0 + i];
+    out->level_points[i] = st[ptr::ST_LP0 + i];
+  }
+  out->atomics = st[ptr::ST_ATOMICS];
+  return PR_OK;
+}
+
+pr_status pr_sync(pr_ctx* ctx) {
+  if (!ctx) return fail(PR_EINVAL, "pr_sync: NULL context");
+  if (pr_status s = set_device(ctx)) return s;
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "pr_sync");
+  HIP_TRY(hipGetLastError(), "pr_sync");
+  return PR_OK;
+}
+
+pr_status pr_cloud_info(const pr_cloud* cloud, uint64_t* n, uint64_t* nbatches, uint32_t* batch_size) {
+  if (!cloud) return fail(PR_EINVAL, "pr_cloud_info: NULL cloud");
+  if (n) *n = cloud->n;
+  if (nbatches) *nbatches = cloud->built ? cloud->nb : 0;
+  if (batch_size) *batch_size = cloud->built ? cloud->batch_size : 0;
+  return PR_OK;
+}
+
+void pr_cloud_free(pr_cloud* cloud) { delete cloud; }
+
+}  // extern "C"

@@ -403,3 +403,9 @@ def test_signed_zero_boxes_use_total_order():
         cmn, cmx = oracle.cloud_aabb(xyz)
         assert cmn.view(np.uint32).tolist()[:2] == [0x80000000] * 2
         assert cmx.view(np.uint32).tolist()[:2] == [0, 0]
+
+
+def test_resolve_foreign_index_gives_clear():
+    colors = np.arange(10, dtype=np.uint32) + 100
+    vb = np.array([3, 10, 0xFFFFFFFF, (0x40000000 << 32) | 9], np.uint64)
+    assert oracle.resolve(vb, colors, 7).tolist() == [103, 7, 7, 109]
