@@ -1,0 +1,293 @@
+#!/usr/bin/env python
+"""Benchmark of the point-rasterization hot path on one MI355X.
+
+Default workload: 2,000,000,000 points of the seeded terrain generator,
+Morton-sorted into batches of 10,240, rendered as a stereo pair of
+2 x 2016 x 2240 (one launch per eye, adaptive 10/20/30-bit precision, batch
+frustum culling).  One step = one stereo frame = for each eye: clear, render,
+resolve.  Inputs are resident in HBM before the timed region; the load-time
+build (Morton sort, batch boxes, Eq. 1 split) is timed separately.
+
+Metric (paper's convention, Sec. 4.1): processed points / frame time, where
+processed points are the points of batches that were not culled (Table 2).
+
+Prints ONE JSON line.  Also reports the render kernel against the HBM roofline
+(algorithmic bytes per launch / measured launch duration) and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpoints/s rendered + achieved HBM GB/s; p50/p99 frame latency in served mode"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name: str, n_override: int | None):
+    import synth
+
+    if name == "c3":
+        n = n_override or 2_000_000_000
+        cams = synth.stereo_cameras(synth.C3_SEED)
+        return dict(name="terrain_2e9_stereo_2x2016x2240", seed=synth.C3_SEED, n=n, morton=True, order=0,
+                    cams=cams, desc=f"terrain {n} points, Morton, 10240-point batches, stereo pair "
+                                    f"2x2016x2240, one launch per eye, adaptive precision, culling on")
+    if name == "c2":
+        n = n_override or 100_000_000
+        cams = [synth.orbit_camera(f) for f in range(0, 60, 15)]
+        return dict(name="terrain_1e8_orbit_1920x1080", seed=synth.C2_SEED, n=n, morton=True, order=1, cams=cams,
+                    desc=f"terrain {n} points, Morton, orbit frames 0/15/30/45 at 1920x1080")
+    if name == "c1":
+        n = n_override or 1_000_000
+        return dict(name="primitives_1e6_1280x720", seed=synth.C1_SEED, n=n, morton=False, order=0,
+                    cams=[synth.c1_camera()], desc=f"8 primitives {n} points, 1280x720")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def load_cloud(ctx, wl, chunk=64_000_000):
+    """Generate the cloud on the host in chunks (pinned, double-buffered) and stream it to HBM."""
+    import numpy as np
+    import torch
+    import paper_2204_01287_amd as pr
+    import synth
+
+    n, S, morton = wl["n"], 10240, wl["morton"]
+    sizes = pr.pr_cloud_sizes(n, S, morton)
+    dev = torch.device("cuda", 0)
+    mem = {f: torch.empty(max(getattr(sizes, f), 256), dtype=torch.uint8, device=dev) for f in pr.DeviceCloud.FIELDS}
+    bufs = pr.CloudBufs(*[mem[f].data_ptr() for f in pr.DeviceCloud.FIELDS], sizes)
+    t0 = time.perf_counter()
+    if wl["name"].startswith("primitives"):
+        xyz, rgba = synth.primitives(wl["seed"], n)
+        mem["xyz"][: 12 * n].copy_(torch.from_numpy(xyz.view(np.uint8).reshape(-1)))
+        mem["rgba"][: 4 * n].copy_(torch.from_numpy(rgba.view(np.uint8)))
+    elif wl["order"] == 1:
+        xyz, rgba = synth.terrain(wl["seed"], n, order=1)
+        mem["xyz"][: 12 * n].copy_(torch.from_numpy(xyz.view(np.uint8).reshape(-1)))
+        mem["rgba"][: 4 * n].copy_(torch.from_numpy(rgba.view(np.uint8)))
+        del xyz, rgba
+    else:
+        chunk = min(chunk, n)
+        host = [(torch.empty(12 * chunk, dtype=torch.uint8, pin_memory=True),
+                 torch.empty(4 * chunk, dtype=torch.uint8, pin_memory=True)) for _ in range(2)]
+        done = [None, None]
+        side = torch.cuda.Stream(dev)
+        for ci, lo in enumerate(range(0, n, chunk)):
+            hi = min(lo + chunk, n)
+            hx, hc = host[ci % 2]
+            if done[ci % 2] is not None:
+                done[ci % 2].synchronize()
+            synth.terrain_range(wl["seed"], n, lo, hi, hx.data_ptr(), hc.data_ptr())
+            with torch.cuda.stream(side):
+                mem["xyz"][12 * lo: 12 * hi].copy_(hx[: 12 * (hi - lo)], non_blocking=True)
+                mem["rgba"][4 * lo: 4 * hi].copy_(hc[: 4 * (hi - lo)], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(side)
+            done[ci % 2] = ev
+            if ci % 8 == 0:
+                log(f"generated {hi / 1e6:.0f}M / {n / 1e6:.0f}M points ({time.perf_counter() - t0:.1f} s)")
+        side.synchronize()
+        del host
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log(f"cloud resident in HBM after {t_gen:.1f} s")
+    handle = pr.pr_load_points(ctx.handle, mem["xyz"], mem["rgba"], n, True, bufs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pr.pr_build_batches(ctx.handle, handle, S, morton)
+    t_build = time.perf_counter() - t1
+    nb = pr.pr_cloud_info(handle)[1]
+    log(f"build (finite check{', Morton sort' if morton else ''}, boxes, Eq. 1 split): {t_build:.2f} s, {nb} batches")
+    return dict(handle=handle, mem=mem, bufs=bufs, n=n, nb=nb, t_gen=t_gen, t_build=t_build)
+
+
+def cpu_baseline(wl, sample_n: int, seconds: float):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    import synth
+
+    t0 = time.perf_counter()
+    if wl["name"].startswith("primitives"):
+        xyz, rgba = synth.primitives(wl["seed"], sample_n)
+    else:
+        xyz, rgba = synth.terrain(wl["seed"], sample_n, order=wl["order"])
+    B = oracle.build_cloud(xyz, rgba, 10240, morton=wl["morton"])
+    t_build = time.perf_counter() - t0
+    pts, secs, frames = 0, 0.0, 0
+    while secs < seconds:
+        for cam in wl["cams"]:
+            t = time.perf_counter()
+            _, st = oracle.render(B, cam.view, cam.proj, cam.width, cam.height)
+            secs += time.perf_counter() - t
+            pts += st["points"]
+            frames += 1
+    return dict(value=round(pts / secs / 1e9, 6), unit="Gpoints/s", cores=1, kind="oracle",
+                sample=f"{wl['name'].split('_')[0]} generator at {sample_n} points (Morton={wl['morton']}), "
+                       f"same cameras and resolution, {frames} oracle renders, {pts} processed points in "
+                       f"{secs:.1f} s; oracle build {t_build:.1f} s not included; single thread")
+
+
+def traffic_from_profiles(kernel_src_hash: str, workload_name: str):
+    """HBM bytes per render launch from committed rocprofv3 --pmc summaries, if they match this kernel."""
+    path = os.path.join(ROOT, "profiles", f"render_{workload_name}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_src_sha256") != kernel_src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def kernel_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kern_render.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2204_01287_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c3")
+    ap.add_argument("--n", type=int, default=None, help="override the point count (smaller test runs)")
+    ap.add_argument("--cpu-sample", type=int, default=32_000_000)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB read + 1 GiB write kernel (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build renders on one GPU only (the multi-GPU sharding is a design, "
+              "not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.add(a, 0.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": a.numel() * 4, "calib_copy_bytes_written": b.numel() * 4,
+                          "launches": 5}))
+        return
+
+    import paper_2204_01287_amd as pr
+
+    wl = workload(args.workload, args.n)
+    ctx = pr.Context(0)
+    cloud = load_cloud(ctx, wl)
+    cams = wl["cams"]
+    vbs = [torch.empty(c.width * c.height, dtype=torch.int64, device="cuda") for c in cams]
+    fbs = [torch.empty(c.width * c.height, dtype=torch.int32, device="cuda") for c in cams]
+
+    # Counters frame (untimed): processed points and precision levels per view.
+    per_view = []
+    for c, vb in zip(cams, vbs):
+        pr.pr_render(ctx.handle, cloud["handle"], c.view, c.proj, c.width, c.height,
+                     pr.RenderOpts.make(counters=1), vb)
+        per_view.append(pr.pr_get_stats(ctx.handle))
+    processed = sum(s["points"] for s in per_view)
+    alg_bytes = [4 * s["level_points"][0] + 8 * s["level_points"][1] + 12 * s["level_points"][2] + 32 * s["batches"]
+                 for s in per_view]
+    log(f"per-view counters: {per_view}")
+
+    acc = pr.RenderOpts.make(accumulate=1)
+    stream = torch.cuda.current_stream()
+    ev = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in cams] for _ in range(args.steps)]
+
+    def frame(step_events=None):
+        for vi, (c, vb, fb) in enumerate(zip(cams, vbs, fbs)):
+            e = step_events[vi] if step_events else None
+            if e:
+                e[0].record(stream)
+            pr.pr_clear(ctx.handle, vb, c.width, c.height)
+            if e:
+                e[1].record(stream)
+            pr.pr_render(ctx.handle, cloud["handle"], c.view, c.proj, c.width, c.height, acc, vb)
+            if e:
+                e[2].record(stream)
+            pr.pr_resolve(ctx.handle, cloud["handle"], vb, c.width, c.height, 0xFF000000, fb)
+            if e:
+                e[3].record(stream)
+
+    for _ in range(args.warmup):
+        frame()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        frame(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pr.pr_sync(ctx.handle)
+
+    step_ms = [ev[s][0][0].elapsed_time(ev[s][-1][3]) for s in range(args.steps)]
+    render_ms = [[ev[s][v][1].elapsed_time(ev[s][v][2]) for s in range(args.steps)] for v in range(len(cams))]
+    clear_ms = [ev[s][v][0].elapsed_time(ev[s][v][1]) for s in range(args.steps) for v in range(len(cams))]
+    resolve_ms = [ev[s][v][2].elapsed_time(ev[s][v][3]) for s in range(args.steps) for v in range(len(cams))]
+    ms_per_step = float(np.mean(step_ms))
+    value = processed / (ms_per_step * 1e-3) / 1e9
+    mean_render = [float(np.mean(r)) for r in render_ms]
+    achieved = sum(alg_bytes) / (sum(mean_render) * 1e-3) / 1e9  # GB/s over the render launches
+    traffic = traffic_from_profiles(kernel_hash(), wl["name"])
+    log(f"wall {wall:.3f} s for {args.steps} steps; events {ms_per_step:.3f} ms/step; render {mean_render} ms; "
+        f"clear {np.mean(clear_ms):.4f} ms; resolve {np.mean(resolve_ms):.4f} ms")
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["name"], "points": wl["n"], "batches": cloud["nb"], "batch_size": 10240,
+                   "views": [f"{c.width}x{c.height}" for c in cams], "precision": "adaptive 10/20/30-bit",
+                   "keys": "u64 depth|index", "description": wl["desc"]},
+        "processed_points_per_step": processed,
+        "all_points_rate_gpts": round(wl["n"] * len(cams) / (ms_per_step * 1e-3) / 1e9, 3),
+        "render_kernel_ms": [round(m, 4) for m in mean_render],
+        "render_only_gpts": round(processed / (sum(mean_render) * 1e-3) / 1e9, 3),
+        "clear_ms": round(float(np.mean(clear_ms)), 4), "resolve_ms": round(float(np.mean(resolve_ms)), 4),
+        "frame_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
+        "frame_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "wall_s_timed": round(wall, 4),
+        "level_points": [sum(s["level_points"][i] for s in per_view) for i in range(3)],
+        "culled_batches": [s["culled"] for s in per_view],
+        "atomics": [s["atomics"] for s in per_view],
+        "load": {"generate_and_upload_s": round(cloud["t_gen"], 2), "build_s": round(cloud["t_build"], 3),
+                 "build_gpts": round(wl["n"] / cloud["t_build"] / 1e9, 3)},
+        "roofline": {"bound": "hbm", "kernel": "render", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_launch": [int(b) for b in alg_bytes],
+                     "traffic": traffic},
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl["n"]), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    pr.pr_cloud_free(cloud["handle"])
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -95,6 +95,9 @@ typedef struct {
   float t10;         /* adaptive: 10 bits if the projected box is < t10 px [500]         */
   float t20;         /* adaptive: 20 bits if < t20 px [512000 = 500 * 2^10], else 30    */
   int32_t counters;  /* 1: accumulate pr_stats for this frame (extra atomics) [0]       */
+  int32_t accumulate;/* 1: do not clear visbuf first; points combine with its content by
+                        minimum, so a sequence of renders into one buffer equals the
+                        elementwise minimum of the separate results [0]               */
 } pr_render_opts;
 
 /* Frame counters (Table 2 definitions): processed batches = every batch,
@@ -138,8 +141,12 @@ pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, ui
  * coordinate is NaN or Inf. */
 pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton);
 
+/* Fill visbuf (uint64[h*w], device, 16-byte aligned) with PR_EMPTY (the
+ * frame clear of Sec. 4.3).  Asynchronous. */
+pr_status pr_clear(pr_ctx* ctx, uint64_t* visbuf, uint32_t w, uint32_t h);
+
 /* Render one view (Sec. 3.2, 3.3): clears visbuf (uint64[h*w], device) to
- * PR_EMPTY, then every batch is culled or rendered at its precision level and
+ * PR_EMPTY (unless opts->accumulate), then every batch is culled or rendered at its precision level and
  * every visible point is combined into visbuf by 64-bit atomic minimum.
  * visbuf must be 16-byte aligned (PR_EINVAL otherwise).  Asynchronous.  PR_ENONFINITE for non-finite matrices, PR_ESTATE before
  * pr_build_batches. */

@@ -12,42 +12,57 @@ struct BatchRec {  // identical layout to pr_batch
 };
 static_assert(sizeof(BatchRec) == 32, "batch record is 32 bytes");
 
-// Frame constants, written by the clear kernel and read by the render kernel:
-// the pixel-space matrix rows (hx, hy, hw) in binary64.
-struct FrameConst {
-  double Pm[3][4];
-};
-
 // Device-side context block (one per pr_ctx), 4 KiB.
 struct DevBlock {
-  FrameConst fc;          // 96 B
-  uint64_t pad0[4];       // keep stats on their own 128-B line
   uint64_t stats[16];     // batches, culled, points, lvl_b[3], lvl_p[3], atomics
   uint32_t flags[16];     // [0] non-finite coordinate seen
 };
 enum { ST_BATCHES = 0, ST_CULLED, ST_POINTS, ST_LB0, ST_LB1, ST_LB2, ST_LP0, ST_LP1, ST_LP2, ST_ATOMICS };
 
-struct ViewArgs {
-  float view[16], proj[16];
+// A batch that survived culling, with everything its workgroup needs
+// (written by the classify kernel, read with scalar loads by the render kernel).
+struct LiveBatch {
+  uint32_t first, count;
+  uint32_t mode;     // level (10, 20, 30) | class << 8 | tiled << 16
+  uint32_t rect_xy;  // tile rectangle origin: x0 | y0 << 16
+  uint32_t rect_wh;  // tile rectangle size: tw | th << 16
+  float P[3][3];     // folded per-batch matrix (binary32)
+  float t[3];
+  uint32_t pad[3];
 };
+static_assert(sizeof(LiveBatch) == 80, "live batch record is 80 bytes");
+
+// Per-frame counters of the render path (in the cloud's scratch area).
+struct FrameHeader {
+  uint32_t live_count;  // live batches written by classify
+  uint32_t work;        // next live batch to hand out (render work queue)
+  uint32_t pad[62];
+};
+static_assert(sizeof(FrameHeader) == 256, "frame header is 256 bytes");
+
+inline uint64_t frame_area_bytes(uint64_t nb) { return sizeof(FrameHeader) + sizeof(LiveBatch) * nb; }
 
 struct RenderArgs {
   const uint32_t* low;
   const uint32_t* med;
   const uint32_t* high;
   const BatchRec* batches;
+  LiveBatch* live;
+  FrameHeader* hdr;
   uint64_t* vb;
-  const DevBlock* dev;
   uint64_t* stats;
+  double Pm[3][4];  // pixel-space matrix rows (hx, hy, hw), binary64
   uint32_t nb, W, H;
   int32_t precision, cull, counters;
   float t10, t20;
+  uint32_t grid;    // persistent render workgroups
 };
 
 // ---- render path (kern_render.hip)
-hipError_t launch_clear(uint64_t* vb, uint64_t npix, const ViewArgs& v, uint32_t W, uint32_t H,
-                        DevBlock* dev, int reset_stats, hipStream_t s);
+hipError_t launch_clear(uint64_t* vb, uint64_t npix, DevBlock* dev, FrameHeader* hdr, int reset_stats, hipStream_t s);
+// classify (cull, level, fold, compaction) followed by the persistent render kernel
 hipError_t launch_render(const RenderArgs& a, hipStream_t s);
+uint32_t render_grid(int device);
 hipError_t launch_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint64_t ncolors,
                           uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
 

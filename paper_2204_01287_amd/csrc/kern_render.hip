@@ -1,4 +1,4 @@
-// Render-path kernels for gfx950: clear (+ per-frame constants), render, resolve.
+// Render-path kernels for gfx950: clear, render, resolve.
 //
 // Method: Schuetz, Kerbl & Wimmer, "Software Rasterization of 2 Billion Points
 // in Real Time", Sec. 3.2 (one workgroup per batch, batch frustum culling,
@@ -6,15 +6,17 @@
 // early-depth test) and Sec. 3.3 (adaptive 10/20/30-bit coordinates, Eq. 1,
 // visibility-buffer resolve).
 //
-// Arithmetic contract (must hold bit for bit; compiled with -ffp-contract=off):
-//  * frame matrix and per-batch decisions in binary64, plain + - * /, left to
-//    right, never fused;
+// Arithmetic contract (bit for bit; compiled with -ffp-contract=off):
+//  * per-batch decisions in binary64, plain + - * /, left to right, never fused;
 //  * per point: X = (float)F (RNE), hx/hy/hw = three fmaf chains in a fixed
 //    order, pixel = exact floor of hx/hw, key = bits(hw) << 32 | index.
 //
-// Each batch is processed by one wave64.  Its prologue projects the 8 box
-// corners (one corner per lane, replicated 8 times), and classifies the batch
-// with wave ballots:
+// Two kernels per view.  The classify kernel runs the per-batch prologue of
+// Sec. 3.2 / 3.3 for every batch at once (one thread per batch): it projects
+// the 8 box corners, culls, picks the precision level, folds the decode into
+// the batch matrix, and appends the surviving batches to a compact list with
+// a wave ballot.  The persistent render kernel then hands the live batches to
+// its workgroups (four waves each) through an atomic work queue.  Classes:
 //  CULLED  : some frustum plane has all corners outside by a margin that
 //            exceeds every rounding of the per-point evaluation;
 //  INSIDE  : all corners strictly inside every plane by that margin and w in
@@ -24,45 +26,40 @@
 //            floor from a reciprocal;
 //  SLOW    : anything else (box reaching w <= 0 or absurd scales): per-point
 //            tests, floor of a correctly rounded binary64 quotient.
-// All three rendering classes give the same result for every point; they only
-// differ in which tests are provably redundant.
+// All classes give the same result for every point; they differ only in
+// which tests are provably redundant.
+//
+// Combining keys.  If the batch lies in front of the eye and its projected
+// box (plus one pixel of margin) covers at most TILE_MAX pixels, the points
+// are first combined by minimum in an LDS tile over that box; afterwards
+// each covered tile pixel goes through the early-depth read and the global
+// atomic minimum once.  The minimum is associative and commutative, so this
+// equals combining every point globally; it replaces one global round trip
+// per point by one per covered pixel.  Larger batches (close to the eye,
+// few points per pixel) combine every point globally.
 #include "internal.h"
 
 namespace ptr {
 namespace {
 
 constexpr int CLS_INSIDE = 0, CLS_PARTIAL = 1, CLS_SLOW = 2;
+constexpr int WAVES = 4;
+constexpr int THREADS = 64 * WAVES;
+constexpr uint32_t TILE_MAX = 4096;  // 32 KiB of 64-bit keys
 
 // ------------------------------------------------------------------ clear
-// Fills the visibility buffer with all-ones (PR_EMPTY), computes the frame's
-// pixel-space matrix, and resets the counters.
+// Fills the visibility buffer with all-ones (PR_EMPTY), resets the frame's
+// work-queue counters and optionally the frame counters.
 __global__ void __launch_bounds__(256) k_clear(uint4* __restrict__ vb4, uint64_t n4, uint64_t* __restrict__ vb,
-                                               uint64_t npix, ViewArgs v, uint32_t W, uint32_t H,
-                                               DevBlock* __restrict__ dev, int reset_stats) {
+                                               uint64_t npix, DevBlock* __restrict__ dev,
+                                               FrameHeader* __restrict__ hdr, int reset_stats) {
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
   for (uint64_t i = tid; i < n4; i += stride) vb4[i] = ones;
   if (tid == 0 && (npix & 1)) vb[npix - 1] = ~0ull;
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) {
-      // C = proj * view for rows 0, 1, 3 (row-major storage, column vectors)
-      double C[3][4];
-      const int rows[3] = {0, 1, 3};
-      for (int q = 0; q < 3; ++q) {
-        const int i = rows[q];
-        for (int j = 0; j < 4; ++j)
-          C[q][j] = (((double)v.proj[4 * i + 0] * (double)v.view[0 + j] +
-                      (double)v.proj[4 * i + 1] * (double)v.view[4 + j]) +
-                     (double)v.proj[4 * i + 2] * (double)v.view[8 + j]) +
-                    (double)v.proj[4 * i + 3] * (double)v.view[12 + j];
-      }
-      for (int j = 0; j < 4; ++j) {
-        dev->fc.Pm[0][j] = (0.5 * (double)W) * (C[0][j] + C[2][j]);
-        dev->fc.Pm[1][j] = (0.5 * (double)H) * (C[1][j] + C[2][j]);
-        dev->fc.Pm[2][j] = C[2][j];
-      }
-    }
+    if (hdr && threadIdx.x < 2) (&hdr->live_count)[threadIdx.x] = 0;
     if (reset_stats && threadIdx.x < 16) dev->stats[threadIdx.x] = 0;
   }
 }
@@ -85,111 +82,147 @@ __device__ __forceinline__ void decode(uint32_t lw, uint32_t mw, uint32_t hw, fl
   }
 }
 
-struct Folded {
-  float P[3][3];
-  float t[3];
+// Frame-wide and batch-wide values of the point loop (uniform: SGPRs).
+struct Loop {
+  float P[3][3], t[3];
+  uint32_t W, H;
+  uint32_t x0, y0, tw, th;  // tile rectangle (tiled batches)
+  uint64_t* vb;
 };
 
-// One point: returns true and fills (off, key) if it lands inside the image.
+// One point: true if it lands inside the image, with its pixel (px, py) and key.
 template <int CLS>
-__device__ __forceinline__ bool project(const Folded& f, float X, float Y, float Z, uint32_t idx, uint32_t W,
-                                        uint32_t H, uint32_t& off, uint64_t& key) {
-  const float hx = __builtin_fmaf(f.P[0][2], Z, __builtin_fmaf(f.P[0][1], Y, __builtin_fmaf(f.P[0][0], X, f.t[0])));
-  const float hy = __builtin_fmaf(f.P[1][2], Z, __builtin_fmaf(f.P[1][1], Y, __builtin_fmaf(f.P[1][0], X, f.t[1])));
-  const float hw = __builtin_fmaf(f.P[2][2], Z, __builtin_fmaf(f.P[2][1], Y, __builtin_fmaf(f.P[2][0], X, f.t[2])));
+__device__ __forceinline__ bool project(const Loop& L, float X, float Y, float Z, uint32_t idx, uint32_t& px,
+                                        uint32_t& py, uint64_t& key) {
+  const float hx = __builtin_fmaf(L.P[0][2], Z, __builtin_fmaf(L.P[0][1], Y, __builtin_fmaf(L.P[0][0], X, L.t[0])));
+  const float hy = __builtin_fmaf(L.P[1][2], Z, __builtin_fmaf(L.P[1][1], Y, __builtin_fmaf(L.P[1][0], X, L.t[1])));
+  const float hw = __builtin_fmaf(L.P[2][2], Z, __builtin_fmaf(L.P[2][1], Y, __builtin_fmaf(L.P[2][0], X, L.t[2])));
   bool ok = true;
   if constexpr (CLS != CLS_INSIDE) {
     // hw > 0, 0 <= hx < W hw, 0 <= hy < H hw; the fma residuals carry the
     // exact sign of hx - W hw (denormals are kept, so nothing underflows to 0).
-    ok = (hw > 0.0f) & (hx >= 0.0f) & (__builtin_fmaf(-(float)W, hw, hx) < 0.0f) & (hy >= 0.0f) &
-         (__builtin_fmaf(-(float)H, hw, hy) < 0.0f);
+    ok = (hw > 0.0f) & (hx >= 0.0f) & (__builtin_fmaf(-(float)L.W, hw, hx) < 0.0f) & (hy >= 0.0f) &
+         (__builtin_fmaf(-(float)L.H, hw, hy) < 0.0f);
   }
-  uint32_t px, py;
   if constexpr (CLS == CLS_SLOW) {
     // Exact floor of the real quotient: the binary64 quotient of two binary32
     // values below 2^13 never crosses an integer.
     px = (uint32_t)floor((double)hx / (double)hw);
     py = (uint32_t)floor((double)hy / (double)hw);
   } else {
-    // n = nearest integer to hx * rcp(hw) is within 1 of the quotient q
-    // (|q - hx rcp(hw)| < 2^-9 for q < 2^13); the sign of the exactly
-    // signed residual hx - n hw decides between n and n - 1.
+    // fma(hx, rcp(hw), 2^23) rounds the exact product to an integer n (the
+    // spacing of floats in [2^23, 2^24) is 1), |n - hx/hw| < 1/2 + 2^-9 for
+    // quotients below 2^13; the exactly signed residual hx - n hw then picks
+    // n or n - 1.  The integer is read from the float's bits.
     const float r = __builtin_amdgcn_rcpf(hw);
-    const float nx = __builtin_rintf(hx * r);
-    const float ny = __builtin_rintf(hy * r);
-    const float ex = __builtin_fmaf(-nx, hw, hx);
-    const float ey = __builtin_fmaf(-ny, hw, hy);
-    px = (uint32_t)nx - (ex < 0.0f ? 1u : 0u);
-    py = (uint32_t)ny - (ey < 0.0f ? 1u : 0u);
+    const float tx = __builtin_fmaf(hx, r, 0x1p23f);
+    const float ty = __builtin_fmaf(hy, r, 0x1p23f);
+    const float ex = __builtin_fmaf(-(tx - 0x1p23f), hw, hx);
+    const float ey = __builtin_fmaf(-(ty - 0x1p23f), hw, hy);
+    px = __float_as_uint(tx) - (0x4B000000u + (ex < 0.0f ? 1u : 0u));
+    py = __float_as_uint(ty) - (0x4B000000u + (ey < 0.0f ? 1u : 0u));
   }
   // Never address outside the image, whatever the class proofs say.
-  ok = ok & (px < W) & (py < H);
-  off = py * W + px;
+  ok = ok & (px < L.W) & (py < L.H);
   key = ((uint64_t)__float_as_uint(hw) << 32) | (uint64_t)idx;
   return ok;
 }
 
-// Four consecutive points of one lane: project all, issue all early-depth
-// reads, then the atomic minimum where the key beats the value read.
-template <int K, int CLS, bool CNT>
-__device__ __forceinline__ void four_points(const Folded& f, uint64_t* __restrict__ vb, uint4 lw, uint4 mw, uint4 hw,
-                                            uint32_t i0, uint32_t nvalid, uint32_t W, uint32_t H,
-                                            uint32_t& natom) {
-  const uint32_t L[4] = {lw.x, lw.y, lw.z, lw.w};
-  const uint32_t M[4] = {mw.x, mw.y, mw.z, mw.w};
-  const uint32_t Hh[4] = {hw.x, hw.y, hw.z, hw.w};
-  uint32_t off[4];
-  uint64_t key[4], old[4];
+__device__ __forceinline__ void global_min(uint64_t* __restrict__ vb, uint32_t off, uint64_t key, uint32_t& natom) {
+  const uint64_t old = __hip_atomic_load(vb + off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  if (key < old) {
+    __hip_atomic_fetch_min(vb + off, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    natom++;
+  }
+}
+
+// Four consecutive points of one lane.
+template <int K, int CLS, bool TILED>
+__device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, uint4 lw, uint4 mw, uint4 hw, uint32_t i0,
+                                            uint32_t nvalid, uint32_t& natom) {
+  const uint32_t Lw[4] = {lw.x, lw.y, lw.z, lw.w};
+  const uint32_t Mw[4] = {mw.x, mw.y, mw.z, mw.w};
+  const uint32_t Hw[4] = {hw.x, hw.y, hw.z, hw.w};
+  uint32_t px[4], py[4];
+  uint64_t key[4];
   bool ok[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     float X, Y, Z;
-    decode<K>(L[j], M[j], Hh[j], X, Y, Z);
-    ok[j] = project<CLS>(f, X, Y, Z, i0 + j, W, H, off[j], key[j]) && ((uint32_t)j < nvalid);
+    decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
+    ok[j] = project<CLS>(L, X, Y, Z, i0 + j, px[j], py[j], key[j]) && ((uint32_t)j < nvalid);
   }
+  if constexpr (TILED) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    old[j] = 0;
-    if (ok[j]) old[j] = __hip_atomic_load(vb + off[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-  }
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t lx = px[j] - L.x0, ly = py[j] - L.y0;
+      if (ok[j] && lx < L.tw && ly < L.th) {
+        __hip_atomic_fetch_min(tile + (ly * L.tw + lx), key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else if (ok[j]) {  // outside the tile rectangle: never for a correct rectangle
+        global_min(L.vb, py[j] * L.W + px[j], key[j], natom);
+      }
+    }
+  } else {
+    // all early-depth reads first, then the atomics
+    uint64_t old[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (ok[j] && key[j] < old[j]) {
-      __hip_atomic_fetch_min(vb + off[j], key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if constexpr (CNT) natom++;
+    for (int j = 0; j < 4; ++j) {
+      old[j] = 0;
+      if (ok[j]) old[j] = __hip_atomic_load(L.vb + (py[j] * L.W + px[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (ok[j] && key[j] < old[j]) {
+        __hip_atomic_fetch_min(L.vb + (py[j] * L.W + px[j]), key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        natom++;
+      }
     }
   }
 }
 
-template <int K, int CLS, bool CNT>
-__device__ void raster_batch(const RenderArgs& a, const Folded& f, uint32_t first, uint32_t count, uint32_t lane) {
+// The points of one batch, split over the workgroup's waves: wave w takes the
+// groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
+// 16-byte load per word, loads issued two groups ahead); wave 0 also takes
+// the ragged tail.
+template <int K, int CLS, bool TILED>
+__device__ void raster_points(const Loop& L, const RenderArgs& a, uint64_t* tile, uint32_t first, uint32_t count,
+                              uint32_t wave, uint32_t lane, uint32_t& natom) {
   const uint4* __restrict__ L4 = reinterpret_cast<const uint4*>(a.low + first);
   const uint4* __restrict__ M4 = reinterpret_cast<const uint4*>(a.med + first);
   const uint4* __restrict__ H4 = reinterpret_cast<const uint4*>(a.high + first);
-  const uint4 zero4 = make_uint4(0, 0, 0, 0);
-  const uint32_t ngrp = count >> 8;  // full groups of 256 points (4 per lane)
-  uint32_t natom = 0;
-  uint4 cl = zero4, cm = zero4, ch = zero4;
-  if (ngrp > 0) {
-    cl = L4[lane];
-    if constexpr (K >= 20) cm = M4[lane];
-    if constexpr (K == 30) ch = H4[lane];
+  const uint4 z4 = make_uint4(0, 0, 0, 0);
+  const uint32_t ngrp = count >> 8;
+  uint4 l0 = z4, m0 = z4, h0 = z4, l1 = z4, m1 = z4, h1 = z4;
+  if (wave < ngrp) {
+    const uint32_t q = wave * 64 + lane;
+    l0 = L4[q];
+    if constexpr (K >= 20) m0 = M4[q];
+    if constexpr (K == 30) h0 = H4[q];
   }
-  for (uint32_t g = 0; g < ngrp; ++g) {
-    uint4 nl = zero4, nm = zero4, nh = zero4;
-    if (g + 1 < ngrp) {  // software prefetch of the next group
-      const uint32_t q = (g + 1) * 64 + lane;
-      nl = L4[q];
-      if constexpr (K >= 20) nm = M4[q];
-      if constexpr (K == 30) nh = H4[q];
+  if (wave + WAVES < ngrp) {
+    const uint32_t q = (wave + WAVES) * 64 + lane;
+    l1 = L4[q];
+    if constexpr (K >= 20) m1 = M4[q];
+    if constexpr (K == 30) h1 = H4[q];
+  }
+  for (uint32_t g = wave; g < ngrp; g += WAVES) {
+    uint4 l2 = z4, m2 = z4, h2 = z4;
+    if (g + 2 * WAVES < ngrp) {
+      const uint32_t q = (g + 2 * WAVES) * 64 + lane;
+      l2 = L4[q];
+      if constexpr (K >= 20) m2 = M4[q];
+      if constexpr (K == 30) h2 = H4[q];
     }
-    four_points<K, CLS, CNT>(f, a.vb, cl, cm, ch, first + g * 256 + lane * 4, 4, a.W, a.H, natom);
-    cl = nl;
-    cm = nm;
-    ch = nh;
+    four_points<K, CLS, TILED>(L, tile, l0, m0, h0, first + g * 256 + lane * 4, 4, natom);
+    l0 = l1;
+    m0 = m1;
+    h0 = h1;
+    l1 = l2;
+    m1 = m2;
+    h1 = h2;
   }
   const uint32_t rem = count & 255u;
-  if (rem) {  // ragged tail of the batch: scalar loads, per-point bounds
+  if (rem && wave == 0) {  // ragged tail of the batch: scalar loads, per-point bounds
     const uint32_t j0 = ngrp * 256 + lane * 4;
     const uint32_t nv = j0 < count ? min(4u, count - j0) : 0u;
     uint32_t l[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0}, h[4] = {0, 0, 0, 0};
@@ -201,136 +234,245 @@ __device__ void raster_batch(const RenderArgs& a, const Folded& f, uint32_t firs
         if constexpr (K == 30) h[j] = a.high[first + j0 + j];
       }
     }
-    four_points<K, CLS, CNT>(f, a.vb, make_uint4(l[0], l[1], l[2], l[3]), make_uint4(m[0], m[1], m[2], m[3]),
-                             make_uint4(h[0], h[1], h[2], h[3]), first + j0, nv, a.W, a.H, natom);
+    four_points<K, CLS, TILED>(L, tile, make_uint4(l[0], l[1], l[2], l[3]), make_uint4(m[0], m[1], m[2], m[3]),
+                               make_uint4(h[0], h[1], h[2], h[3]), first + j0, nv, natom);
+  }
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ---------------------------------------------------------------- classify
+// The per-batch prologue (Sec. 3.2 culling, Sec. 3.3 precision choice) for one
+// batch per thread, in binary64 without contraction:
+//  corners  h_r(c) = ((Pm[r][0] cx + Pm[r][1] cy) + Pm[r][2] cz) + Pm[r][3]
+//  margin   M_r = 2^-16 max_c (|Pm[r][0] cx| + |Pm[r][1] cy| + |Pm[r][2] cz| + |Pm[r][3]|),
+//           which exceeds every rounding of the binary32 per-point evaluation
+//           (below 2^-20 of that sum);
+//  cull     all corners outside one plane by the margin;
+//  level    E = larger side of the projected corners' box (+inf if a corner
+//           has w <= 0); 10 bits if E < t10, 20 if E < t20, else 30;
+//  fold     P[r][j] = fp32(Pm[r][j] (size_j 2^-k)),
+//           t[r] = fp32(((Pm[r][0] min_x + Pm[r][1] min_y) + Pm[r][2] min_z) + Pm[r][3]).
+// Live batches are appended to a compact list (wave ballot + one atomic per wave).
+template <bool CNT>
+__global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
+  const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
+  const bool valid = b < a.nb;
+  bool live = false;
+  LiveBatch out;
+  uint32_t count = 0;
+  int li = 0;
+  bool culled = false;
+  if (valid) {
+    const BatchRec rec = a.batches[b];
+    count = rec.count;
+    const double(&Pm)[3][4] = a.Pm;
+    double H[3][8], M[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double amax = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double cx = (double)((c & 1) ? rec.mx[0] : rec.mn[0]);
+        const double cy = (double)((c & 2) ? rec.mx[1] : rec.mn[1]);
+        const double cz = (double)((c & 4) ? rec.mx[2] : rec.mn[2]);
+        H[r][c] = ((Pm[r][0] * cx + Pm[r][1] * cy) + Pm[r][2] * cz) + Pm[r][3];
+        const double ar = ((fabs(Pm[r][0] * cx) + fabs(Pm[r][1] * cy)) + fabs(Pm[r][2] * cz)) + fabs(Pm[r][3]);
+        if (ar > amax) amax = ar;
+      }
+      M[r] = 0x1p-16 * amax;
+    }
+    const double Wd = (double)a.W, Hd = (double)a.H;
+    bool behind = true, left = true, right = true, bottom = true, top = true, front = true;
+    bool safe = true, ins = true;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      behind = behind && (H[2][c] < -M[2]);
+      left = left && (H[0][c] < -M[0]);
+      right = right && (H[0][c] - Wd * H[2][c] > M[0] + Wd * M[2]);
+      bottom = bottom && (H[1][c] < -M[1]);
+      top = top && (H[1][c] - Hd * H[2][c] > M[1] + Hd * M[2]);
+      front = front && (H[2][c] > 0.0);
+      const bool sc = (H[2][c] - M[2] >= 0x1p-60) && (H[2][c] + M[2] <= 0x1p60);
+      safe = safe && sc;
+      ins = ins && sc && (H[0][c] > M[0]) && (H[0][c] - Wd * H[2][c] < -(M[0] + Wd * M[2])) && (H[1][c] > M[1]) &&
+            (H[1][c] - Hd * H[2][c] < -(M[1] + Hd * M[2]));
+    }
+    culled = a.cull && (behind || left || right || bottom || top);
+    if (!culled) {
+      double umin = __builtin_inf(), umax = -__builtin_inf(), vmin = __builtin_inf(), vmax = -__builtin_inf();
+      if (front) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const double u = H[0][c] / H[2][c], v = H[1][c] / H[2][c];
+          if (u < umin) umin = u;
+          if (u > umax) umax = u;
+          if (v < vmin) vmin = v;
+          if (v > vmax) vmax = v;
+        }
+      }
+      int k;
+      if (a.precision == 10 || a.precision == 20 || a.precision == 30) {
+        k = a.precision;
+      } else {
+        double E = __builtin_inf();
+        if (front) {
+          const double ex = umax - umin, ey = vmax - vmin;
+          E = ex > ey ? ex : ey;
+        }
+        k = E < (double)a.t10 ? 10 : (E < (double)a.t20 ? 20 : 30);
+      }
+      const int cls = ins ? CLS_INSIDE : (safe ? CLS_PARTIAL : CLS_SLOW);
+      // Tile rectangle: the projected corners' box, one pixel wider on each
+      // side, clipped to the image (front batches only).
+      uint32_t tiled = 0, x0 = 0, y0 = 0, tw = 0, th = 0;
+      if (front && cls != CLS_SLOW) {
+        const double fx0 = fmax(floor(fmax(umin, -4.0)) - 1.0, 0.0);
+        const double fx1 = fmin(floor(fmin(umax, Wd + 4.0)) + 1.0, Wd - 1.0);
+        const double fy0 = fmax(floor(fmax(vmin, -4.0)) - 1.0, 0.0);
+        const double fy1 = fmin(floor(fmin(vmax, Hd + 4.0)) + 1.0, Hd - 1.0);
+        if (fx1 >= fx0 && fy1 >= fy0 && (fx1 - fx0 + 1.0) * (fy1 - fy0 + 1.0) <= (double)TILE_MAX) {
+          tiled = 1;
+          x0 = (uint32_t)fx0;
+          y0 = (uint32_t)fy0;
+          tw = (uint32_t)(fx1 - fx0) + 1u;
+          th = (uint32_t)(fy1 - fy0) + 1u;
+        }
+      }
+      const double scale = k == 10 ? 0x1p-10 : (k == 20 ? 0x1p-20 : 0x1p-30);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) out.P[r][j] = (float)(Pm[r][j] * (((double)rec.mx[j] - (double)rec.mn[j]) * scale));
+        out.t[r] = (float)(((Pm[r][0] * (double)rec.mn[0] + Pm[r][1] * (double)rec.mn[1]) +
+                            Pm[r][2] * (double)rec.mn[2]) +
+                           Pm[r][3]);
+      }
+      out.first = rec.first;
+      out.count = rec.count;
+      out.mode = (uint32_t)k | ((uint32_t)cls << 8) | (tiled << 16);
+      out.rect_xy = x0 | (y0 << 16);
+      out.rect_wh = tw | (th << 16);
+      out.pad[0] = out.pad[1] = out.pad[2] = 0;
+      live = true;
+      li = k / 10 - 1;
+    }
+  }
+  if constexpr (CNT) {
+    const uint64_t mv = __ballot(valid), mc = __ballot(valid && culled);
+    uint64_t pts = live ? count : 0, lp[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+    if (live) {
+      lp[li] = count;
+      lb[li] = 1;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      pts += __shfl_xor(pts, o);
+      for (int q = 0; q < 3; ++q) {
+        lp[q] += __shfl_xor(lp[q], o);
+        lb[q] += __shfl_xor(lb[q], o);
+      }
+    }
+    if (lane == 0 && mv) {
+      atomicAdd((unsigned long long*)&a.stats[ST_BATCHES], (unsigned long long)__popcll(mv));
+      if (mc) atomicAdd((unsigned long long*)&a.stats[ST_CULLED], (unsigned long long)__popcll(mc));
+      if (pts) atomicAdd((unsigned long long*)&a.stats[ST_POINTS], (unsigned long long)pts);
+      for (int q = 0; q < 3; ++q) {
+        if (lb[q]) atomicAdd((unsigned long long*)&a.stats[ST_LB0 + q], (unsigned long long)lb[q]);
+        if (lp[q]) atomicAdd((unsigned long long*)&a.stats[ST_LP0 + q], (unsigned long long)lp[q]);
+      }
+    }
+  }
+  const uint64_t m = __ballot(live);
+  uint32_t base = 0;
+  if (lane == 0 && m) base = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(m));
+  base = __shfl(base, 0);
+  if (live) {
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    a.live[base + (uint32_t)__popcll(m & lt)] = out;
+  }
+}
+
+// ------------------------------------------------------------------ render
+template <int K, bool TILED>
+__device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const RenderArgs& a, uint64_t* tile,
+                                                uint32_t first, uint32_t count, uint32_t wave, uint32_t lane,
+                                                uint32_t& natom) {
+  if (cls == CLS_INSIDE)
+    raster_points<K, CLS_INSIDE, TILED>(L, a, tile, first, count, wave, lane, natom);
+  else if (cls == CLS_PARTIAL)
+    raster_points<K, CLS_PARTIAL, TILED>(L, a, tile, first, count, wave, lane, natom);
+  else if constexpr (!TILED)
+    raster_points<K, CLS_SLOW, false>(L, a, tile, first, count, wave, lane, natom);
+}
+
+// Persistent: each workgroup takes live batches from the work queue until it
+// is empty.  The LDS tile is all PR_EMPTY between batches (the flush resets
+// what it reads), so a batch needs two barriers: one after its points, one
+// after its flush.
+template <bool CNT>
+__global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
+  __shared__ uint64_t tile[TILE_MAX];
+  __shared__ uint32_t s_next;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+  for (uint32_t e = tid; e < TILE_MAX / 2; e += THREADS) reinterpret_cast<uint4*>(tile)[e] = ones;
+  if (tid == 0) s_next = atomicAdd(&a.hdr->work, 1u);
+  const uint32_t nlive = a.hdr->live_count;
+  __syncthreads();
+  uint32_t i = uni(s_next);
+  uint32_t natom = 0;
+  while (i < nlive) {
+    const LiveBatch& rec = a.live[i];
+    Loop L;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) L.P[r][j] = rec.P[r][j];
+      L.t[r] = rec.t[r];
+    }
+    L.W = a.W;
+    L.H = a.H;
+    L.vb = a.vb;
+    const uint32_t mode = rec.mode, rxy = rec.rect_xy, rwh = rec.rect_wh;
+    const uint32_t first = rec.first, count = rec.count;
+    L.x0 = rxy & 0xFFFFu;
+    L.y0 = rxy >> 16;
+    L.tw = rwh & 0xFFFFu;
+    L.th = rwh >> 16;
+    const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
+    const bool tiled = (mode >> 16) & 1u;
+    if (tiled) {
+      if (k == 10) raster_by_class<10, true>(cls, L, a, tile, first, count, wave, lane, natom);
+      else if (k == 20) raster_by_class<20, true>(cls, L, a, tile, first, count, wave, lane, natom);
+      else raster_by_class<30, true>(cls, L, a, tile, first, count, wave, lane, natom);
+    } else {
+      if (k == 10) raster_by_class<10, false>(cls, L, a, tile, first, count, wave, lane, natom);
+      else if (k == 20) raster_by_class<20, false>(cls, L, a, tile, first, count, wave, lane, natom);
+      else raster_by_class<30, false>(cls, L, a, tile, first, count, wave, lane, natom);
+    }
+    __syncthreads();  // the batch's points are all in the tile; s_next has been read
+    if (tid == 0) s_next = atomicAdd(&a.hdr->work, 1u);
+    if (tiled) {
+      // Flush: every covered tile pixel once through early depth + global
+      // minimum, leaving the entry PR_EMPTY for the next batch.
+      const uint32_t n = L.tw * L.th;
+      for (uint32_t e = tid; e < n; e += THREADS) {
+        const uint64_t v = tile[e];
+        if (v != ~0ull) {
+          tile[e] = ~0ull;
+          const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
+          global_min(L.vb, (L.y0 + ly) * L.W + (L.x0 + lx), v, natom);
+        }
+      }
+    }
+    __syncthreads();  // tile clean again; s_next visible
+    i = uni(s_next);
   }
   if constexpr (CNT) {
     for (int o = 32; o > 0; o >>= 1) natom += __shfl_xor(natom, o);
     if (lane == 0 && natom) atomicAdd((unsigned long long*)&a.stats[ST_ATOMICS], (unsigned long long)natom);
   }
-}
-
-__device__ __forceinline__ double max8(double v) {
-  v = fmax(v, __shfl_xor(v, 1));
-  v = fmax(v, __shfl_xor(v, 2));
-  v = fmax(v, __shfl_xor(v, 4));
-  return v;
-}
-__device__ __forceinline__ double min8(double v) {
-  v = fmin(v, __shfl_xor(v, 1));
-  v = fmin(v, __shfl_xor(v, 2));
-  v = fmin(v, __shfl_xor(v, 4));
-  return v;
-}
-__device__ __forceinline__ float uniform_f(float x) {
-  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x)));
-}
-
-template <bool CNT>
-__device__ void render_one_batch(const RenderArgs& a, uint32_t b, uint32_t lane) {
-  const BatchRec rec = a.batches[b];
-  double Pm[3][4];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Pm[r][j] = a.dev->fc.Pm[r][j];
-
-  // ---- corners: lane c (mod 8) takes corner c of [min, max]
-  const int c = lane & 7;
-  const double cx = (double)((c & 1) ? rec.mx[0] : rec.mn[0]);
-  const double cy = (double)((c & 2) ? rec.mx[1] : rec.mn[1]);
-  const double cz = (double)((c & 4) ? rec.mx[2] : rec.mn[2]);
-  double Hc[3], M[3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    Hc[r] = ((Pm[r][0] * cx + Pm[r][1] * cy) + Pm[r][2] * cz) + Pm[r][3];
-    const double ar = ((fabs(Pm[r][0] * cx) + fabs(Pm[r][1] * cy)) + fabs(Pm[r][2] * cz)) + fabs(Pm[r][3]);
-    M[r] = 0x1p-16 * max8(ar);
-  }
-  const double Wd = (double)a.W, Hd = (double)a.H;
-  const uint64_t full = __ballot(1);
-  const bool behind = __ballot(Hc[2] < -M[2]) == full;
-  const bool left = __ballot(Hc[0] < -M[0]) == full;
-  const bool right = __ballot(Hc[0] - Wd * Hc[2] > M[0] + Wd * M[2]) == full;
-  const bool bottom = __ballot(Hc[1] < -M[1]) == full;
-  const bool top = __ballot(Hc[1] - Hd * Hc[2] > M[1] + Hd * M[2]) == full;
-  const bool culled = a.cull && (behind | left | right | bottom | top);
-
-  if constexpr (CNT) {
-    if (lane == 0) {
-      atomicAdd((unsigned long long*)&a.stats[ST_BATCHES], 1ull);
-      if (culled) atomicAdd((unsigned long long*)&a.stats[ST_CULLED], 1ull);
-    }
-  }
-  if (culled) return;
-
-  // ---- precision level (Sec. 3.3: < 500 px -> 10 bits)
-  int k;
-  if (a.precision == 10 || a.precision == 20 || a.precision == 30) {
-    k = a.precision;
-  } else {
-    const bool front = __ballot(Hc[2] > 0.0) == full;
-    double E = __builtin_inf();
-    if (front) {
-      const double u = Hc[0] / Hc[2], v = Hc[1] / Hc[2];
-      const double ex = max8(u) - min8(u), ey = max8(v) - min8(v);
-      E = ex > ey ? ex : ey;
-    }
-    k = E < (double)a.t10 ? 10 : (E < (double)a.t20 ? 20 : 30);
-  }
-
-  // ---- class of the per-point tests
-  const bool safe = (Hc[2] - M[2] >= 0x1p-60) && (Hc[2] + M[2] <= 0x1p60);
-  const bool ins = safe && (Hc[0] > M[0]) && (Hc[0] - Wd * Hc[2] < -(M[0] + Wd * M[2])) && (Hc[1] > M[1]) &&
-                   (Hc[1] - Hd * Hc[2] < -(M[1] + Hd * M[2]));
-  const int cls = (__ballot(ins) == full) ? CLS_INSIDE : ((__ballot(safe) == full) ? CLS_PARTIAL : CLS_SLOW);
-
-  // ---- fold decode into the matrix: P[r][j] = fp32(Pm[r][j] (size_j 2^-k)),
-  //      t[r] = fp32(Pm[r] . min + Pm[r][3])  (lower-corner decode)
-  const double scale = k == 10 ? 0x1p-10 : (k == 20 ? 0x1p-20 : 0x1p-30);
-  const double s[3] = {(double)rec.mx[0] - (double)rec.mn[0], (double)rec.mx[1] - (double)rec.mn[1],
-                       (double)rec.mx[2] - (double)rec.mn[2]};
-  Folded f;
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) f.P[r][j] = uniform_f((float)(Pm[r][j] * (s[j] * scale)));
-    f.t[r] = uniform_f((float)(((Pm[r][0] * (double)rec.mn[0] + Pm[r][1] * (double)rec.mn[1]) +
-                                Pm[r][2] * (double)rec.mn[2]) +
-                               Pm[r][3]));
-  }
-
-  if constexpr (CNT) {
-    if (lane == 0) {
-      const int li = k / 10 - 1;
-      atomicAdd((unsigned long long*)&a.stats[ST_POINTS], (unsigned long long)rec.count);
-      atomicAdd((unsigned long long*)&a.stats[ST_LB0 + li], 1ull);
-      atomicAdd((unsigned long long*)&a.stats[ST_LP0 + li], (unsigned long long)rec.count);
-    }
-  }
-
-  const uint32_t first = rec.first, count = rec.count;
-  if (k == 10) {
-    if (cls == CLS_INSIDE) raster_batch<10, CLS_INSIDE, CNT>(a, f, first, count, lane);
-    else if (cls == CLS_PARTIAL) raster_batch<10, CLS_PARTIAL, CNT>(a, f, first, count, lane);
-    else raster_batch<10, CLS_SLOW, CNT>(a, f, first, count, lane);
-  } else if (k == 20) {
-    if (cls == CLS_INSIDE) raster_batch<20, CLS_INSIDE, CNT>(a, f, first, count, lane);
-    else if (cls == CLS_PARTIAL) raster_batch<20, CLS_PARTIAL, CNT>(a, f, first, count, lane);
-    else raster_batch<20, CLS_SLOW, CNT>(a, f, first, count, lane);
-  } else {
-    if (cls == CLS_INSIDE) raster_batch<30, CLS_INSIDE, CNT>(a, f, first, count, lane);
-    else if (cls == CLS_PARTIAL) raster_batch<30, CLS_PARTIAL, CNT>(a, f, first, count, lane);
-    else raster_batch<30, CLS_SLOW, CNT>(a, f, first, count, lane);
-  }
-}
-
-// One wave64 workgroup per batch (Sec. 3.2: one workgroup per batch).
-template <bool CNT>
-__global__ void __launch_bounds__(64) k_render(RenderArgs a) {
-  const uint32_t b = blockIdx.x;
-  if (b >= a.nb) return;
-  render_one_batch<CNT>(a, b, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ resolve
@@ -363,23 +505,35 @@ __global__ void __launch_bounds__(256) k_resolve(const uint64_t* __restrict__ vb
 
 }  // namespace
 
-hipError_t launch_clear(uint64_t* vb, uint64_t npix, const ViewArgs& v, uint32_t W, uint32_t H, DevBlock* dev,
-                        int reset_stats, hipStream_t s) {
+hipError_t launch_clear(uint64_t* vb, uint64_t npix, DevBlock* dev, FrameHeader* hdr, int reset_stats, hipStream_t s) {
   const uint64_t n4 = npix / 2;
   uint64_t blocks = (n4 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_clear, dim3((uint32_t)blocks), dim3(256), 0, s, reinterpret_cast<uint4*>(vb), n4, vb, npix, v,
-                     W, H, dev, reset_stats);
+  hipLaunchKernelGGL(k_clear, dim3((uint32_t)blocks), dim3(256), 0, s, reinterpret_cast<uint4*>(vb), n4, vb, npix,
+                     dev, hdr, reset_stats);
   return hipGetLastError();
+}
+
+uint32_t render_grid(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render<false>, THREADS, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  return (uint32_t)(per_cu * cus);
 }
 
 hipError_t launch_render(const RenderArgs& a, hipStream_t s) {
   if (a.nb == 0) return hipSuccess;
-  if (a.counters)
-    hipLaunchKernelGGL(k_render<true>, dim3(a.nb), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_render<false>, dim3(a.nb), dim3(64), 0, s, a);
+  const uint32_t cblocks = (a.nb + 255) / 256;
+  const uint32_t rblocks = a.grid < a.nb ? a.grid : a.nb;
+  if (a.counters) {
+    hipLaunchKernelGGL(k_classify<true>, dim3(cblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_render<true>, dim3(rblocks), dim3(THREADS), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_classify<false>, dim3(cblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_render<false>, dim3(rblocks), dim3(THREADS), 0, s, a);
+  }
   return hipGetLastError();
 }
 

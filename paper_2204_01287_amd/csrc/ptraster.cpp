@@ -17,7 +17,8 @@
 struct pr_ctx {
   int device;
   hipStream_t stream;
-  ptr::DevBlock* dev;  // frame constants, counters, flags (device memory)
+  ptr::DevBlock* dev;  // counters and flags (device memory)
+  uint32_t render_grid;  // persistent render workgroups that fit on the device at once
 };
 
 struct pr_cloud {
@@ -73,6 +74,28 @@ pr_status set_device(const pr_ctx* ctx) {
   return PR_OK;
 }
 
+// Pixel-space matrix (Sec. 3.2 projection; the paper leaves toPixelID open):
+// C = proj * view (row-major storage, column vectors); window x =
+// (x_clip / w_clip + 1) W / 2, so the rows are hx = (W/2)(C0 + C3),
+// hy = (H/2)(C1 + C3), hw = C3.  binary64, sums left to right, no fused
+// multiply-add (this file is compiled with -ffp-contract=off).
+void frame_matrix(const float* view, const float* proj, uint32_t w, uint32_t h, double Pm[3][4]) {
+  double C[3][4];
+  const int rows[3] = {0, 1, 3};
+  for (int q = 0; q < 3; ++q) {
+    const int i = rows[q];
+    for (int j = 0; j < 4; ++j)
+      C[q][j] = (((double)proj[4 * i + 0] * (double)view[0 + j] + (double)proj[4 * i + 1] * (double)view[4 + j]) +
+                 (double)proj[4 * i + 2] * (double)view[8 + j]) +
+                (double)proj[4 * i + 3] * (double)view[12 + j];
+  }
+  for (int j = 0; j < 4; ++j) {
+    Pm[0][j] = (0.5 * (double)w) * (C[0][j] + C[2][j]);
+    Pm[1][j] = (0.5 * (double)h) * (C[1][j] + C[2][j]);
+    Pm[2][j] = C[2][j];
+  }
+}
+
 pr_status sizes_for(uint64_t n, uint32_t batch_size, int morton, pr_sizes* s) {
   if (batch_size == 0 || (batch_size & 3u)) return fail(PR_EINVAL, "batch_size %u must be a positive multiple of 4", batch_size);
   if (n > kMaxPoints - 1) return fail(PR_ERANGE, "n = %llu points: at most 2^32 - 1", (unsigned long long)n);
@@ -81,7 +104,10 @@ pr_status sizes_for(uint64_t n, uint32_t batch_size, int morton, pr_sizes* s) {
   s->rgba = a256(4 * n);
   s->low = s->med = s->high = s->colors = s->perm = a256(4 * n);
   s->batches = a256(32 * nb);
-  s->scratch = a256(ptr::small_scratch_bytes() + (morton ? ptr::sort_scratch_layout(n, nullptr, nullptr) : 0));
+  // Load-time sort area and per-frame area (live batch list) share the space.
+  const uint64_t sort = morton ? ptr::sort_scratch_layout(n, nullptr, nullptr) : 0;
+  const uint64_t frame = ptr::frame_area_bytes(nb);
+  s->scratch = a256(ptr::small_scratch_bytes() + (sort > frame ? sort : frame));
   return PR_OK;
 }
 
@@ -108,6 +134,7 @@ pr_status pr_create(int device, void* hip_stream, pr_ctx** out) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->dev = nullptr;
+  c->render_grid = ptr::render_grid(device);
   e = hipMalloc(reinterpret_cast<void**>(&c->dev), 4096);
   if (e != hipSuccess) {
     delete c;
@@ -236,7 +263,7 @@ pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], co
   if (!cloud->built) return fail(PR_ESTATE, "pr_render: cloud is not built (call pr_build_batches)");
   if (pr_status s = check_dims(w, h)) return s;
   if (reinterpret_cast<uintptr_t>(visbuf) & 15u) return fail(PR_EINVAL, "pr_render: visbuf must be 16-byte aligned");
-  pr_render_opts o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0};
+  pr_render_opts o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0};
   if (opts) o = *opts;
   if (o.precision != PR_ADAPTIVE && o.precision != PR_FORCE10 && o.precision != PR_FORCE20 &&
       o.precision != PR_FORCE30)
@@ -245,19 +272,23 @@ pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], co
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(view[i]) || !std::isfinite(proj[i])) return fail(PR_ENONFINITE, "pr_render: non-finite matrix");
   if (pr_status s = set_device(ctx)) return s;
-  ptr::ViewArgs va;
-  std::memcpy(va.view, view, sizeof va.view);
-  std::memcpy(va.proj, proj, sizeof va.proj);
   const uint64_t npix = (uint64_t)w * h;
-  HIP_TRY(ptr::launch_clear(visbuf, npix, va, w, h, ctx->dev, o.counters ? 1 : 0, ctx->stream), "clear");
+  ptr::FrameHeader* hdr =
+      reinterpret_cast<ptr::FrameHeader*>(static_cast<uint8_t*>(cloud->bufs.scratch) + ptr::small_scratch_bytes());
+  // clear (or, when accumulating, only reset the frame's work queue and counters)
+  HIP_TRY(ptr::launch_clear(visbuf, o.accumulate ? 0 : npix, ctx->dev, hdr, o.counters ? 1 : 0, ctx->stream),
+          "clear");
   ptr::RenderArgs a;
   a.low = static_cast<const uint32_t*>(cloud->bufs.low);
   a.med = static_cast<const uint32_t*>(cloud->bufs.med);
   a.high = static_cast<const uint32_t*>(cloud->bufs.high);
   a.batches = static_cast<const ptr::BatchRec*>(cloud->bufs.batches);
+  a.hdr = hdr;
+  a.live = reinterpret_cast<ptr::LiveBatch*>(hdr + 1);
+  a.grid = ctx->render_grid;
   a.vb = visbuf;
-  a.dev = ctx->dev;
   a.stats = ctx->dev->stats;
+  frame_matrix(view, proj, w, h, a.Pm);
   a.nb = (uint32_t)cloud->nb;
   a.W = w;
   a.H = h;
@@ -267,6 +298,15 @@ pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], co
   a.t10 = o.t10;
   a.t20 = o.t20;
   HIP_TRY(ptr::launch_render(a, ctx->stream), "render");
+  return PR_OK;
+}
+
+pr_status pr_clear(pr_ctx* ctx, uint64_t* visbuf, uint32_t w, uint32_t h) {
+  if (!ctx || !visbuf) return fail(PR_EINVAL, "pr_clear: NULL argument");
+  if (pr_status s = check_dims(w, h)) return s;
+  if (reinterpret_cast<uintptr_t>(visbuf) & 15u) return fail(PR_EINVAL, "pr_clear: visbuf must be 16-byte aligned");
+  if (pr_status s = set_device(ctx)) return s;
+  HIP_TRY(ptr::launch_clear(visbuf, (uint64_t)w * h, ctx->dev, nullptr, 0, ctx->stream), "clear");
   return PR_OK;
 }
 

@@ -44,6 +44,9 @@ def _load():
         lib.synth_terrain.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.synth_terrain.restype = ctypes.c_int
+        lib.synth_terrain_range.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.synth_terrain_range.restype = ctypes.c_int
         lib.synth_terrain_height.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double]
         lib.synth_terrain_height.restype = ctypes.c_double
         _lib = lib
@@ -77,6 +80,15 @@ def terrain(seed: int, n: int, sigma: float = 0.01, order: int = 1, threads: int
     if rc != 0:
         raise RuntimeError(f"synth_terrain failed ({rc})")
     return xyz, rgba
+
+
+def terrain_range(seed: int, n: int, lo: int, hi: int, xyz_ptr: int, rgba_ptr: int, sigma: float = 0.01,
+                  threads: int = 0) -> None:
+    """Points [lo, hi) of the index-order terrain of n points into raw host buffers
+    (float32[hi-lo][3] at xyz_ptr, uint32[hi-lo] at rgba_ptr)."""
+    rc = _load().synth_terrain_range(seed, n, lo, hi, sigma, xyz_ptr, rgba_ptr, threads)
+    if rc != 0:
+        raise RuntimeError(f"synth_terrain_range failed ({rc})")
 
 
 def terrain_height(seed: int, x: float, y: float) -> float:

@@ -348,6 +348,41 @@ static void bucket_scatter(void* arg, uint64_t lo, uint64_t hi) {
   }
 }
 
+/* Points [lo, hi) of the index-order terrain cloud of n points, written to
+ * xyz[0 .. 3(hi-lo)) and rgba[0 .. hi-lo): lets a very large cloud be produced
+ * in chunks (identical bytes to synth_terrain(order = 0)). */
+int synth_terrain_range(uint64_t seed, uint64_t n, uint64_t lo, uint64_t hi, double sigma, float* xyz,
+                        uint32_t* rgba, int nthreads) {
+  if (!xyz || !rgba || lo > hi || hi > n) return -1;
+  terrain_job J;
+  memset(&J, 0, sizeof J);
+  J.seed = seed; J.n = n; J.sigma = sigma;
+  J.n_ground = (uint64_t)((double)n * 0.80);
+  J.n_build = (uint64_t)((double)n * 0.96);
+  J.B = (building_t*)malloc(sizeof(building_t) * N_BUILDINGS);
+  J.Q = (pole_t*)malloc(sizeof(pole_t) * N_POLES);
+  if (!J.B || !J.Q) { free(J.B); free(J.Q); return -2; }
+  make_scene(seed, J.B, J.Q);
+  /* shift the output pointers so that point i lands at index i - lo */
+  J.xyz = xyz - 3 * lo;
+  J.rgba = rgba - lo;
+  range_job jobs[256];
+  pthread_t th[256];
+  int t = pick_threads(nthreads);
+  uint64_t cnt = hi - lo;
+  if ((uint64_t)t > cnt) t = cnt ? (int)cnt : 1;
+  for (int k = 0; k < t; ++k) {
+    jobs[k].fn = terrain_range; jobs[k].arg = &J;
+    jobs[k].lo = lo + cnt * (uint64_t)k / (uint64_t)t;
+    jobs[k].hi = lo + cnt * (uint64_t)(k + 1) / (uint64_t)t;
+  }
+  for (int k = 1; k < t; ++k) pthread_create(&th[k], NULL, range_thread, &jobs[k]);
+  range_thread(&jobs[0]);
+  for (int k = 1; k < t; ++k) pthread_join(th[k], NULL);
+  free(J.B); free(J.Q);
+  return 0;
+}
+
 /* order: 0 = index order (ground, then buildings, then poles);
  *        1 = stable serpentine 10 m tile order.
  * Returns 0, or -1 on bad arguments, -2 if temporary memory is unavailable. */

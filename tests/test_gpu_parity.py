@@ -247,3 +247,27 @@ def test_non_finite_inputs(ctx):
     with pytest.raises(pr.PrError) as e:
         pr.pr_render(ctx.handle, dc.handle, cam.view, cam.proj, 0, 8, None, vb)
     assert e.value.name == "PR_ERANGE"
+
+
+def test_clear_and_accumulate(ctx, c1):
+    """pr_clear + accumulate render == plain render; two views accumulate to the elementwise minimum."""
+    import torch
+    import paper_2204_01287_amd as pr
+
+    dc, B = c1
+    cam = synth.c1_camera()
+    other = synth.random_camera(np.random.default_rng(12), cam.width, cam.height)
+    w, h = cam.width, cam.height
+    vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
+    say("clear + accumulate")
+    pr.pr_clear(ctx.handle, vb, w, h)
+    acc = pr.RenderOpts.make(accumulate=1)
+    pr.pr_render(ctx.handle, dc.handle, cam.view, cam.proj, w, h, acc, vb)
+    pr.pr_sync(ctx.handle)
+    one = vb.cpu().numpy().view(np.uint64).copy()
+    ref_a, _ = oracle.render(B, cam.view, cam.proj, w, h)
+    assert_vb_equal(one, ref_a, w)
+    pr.pr_render(ctx.handle, dc.handle, other.view, other.proj, w, h, acc, vb)
+    pr.pr_sync(ctx.handle)
+    ref_b, _ = oracle.render(B, other.view, other.proj, w, h)
+    assert_vb_equal(vb.cpu().numpy().view(np.uint64), np.minimum(ref_a, ref_b), w)

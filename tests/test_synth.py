@@ -39,3 +39,13 @@ def test_terrain_category_mix():
     g = xyz[:80_000:997]
     h = np.array([synth.terrain_height(5, float(x), float(y)) for x, y, _ in g])
     assert np.abs(g[:, 2] - h).max() < 0.1
+
+
+def test_terrain_range_matches_whole_cloud():
+    n = 123_457
+    xyz, rgba = synth.terrain(6, n, order=0)
+    for lo, hi in ((0, 1000), (5000, 70001), (n - 17, n)):
+        x = np.empty((hi - lo, 3), np.float32)
+        c = np.empty(hi - lo, np.uint32)
+        synth.terrain_range(6, n, lo, hi, x.ctypes.data, c.ctypes.data, threads=3)
+        assert np.array_equal(x, xyz[lo:hi]) and np.array_equal(c, rgba[lo:hi])
