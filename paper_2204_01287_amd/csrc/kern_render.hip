@@ -31,9 +31,9 @@
 //
 // Combining keys.  If the batch lies in front of the eye and its projected
 // box (plus one pixel of margin) covers at most TILE_MAX pixels, the points
-// are first combined by minimum in an LDS tile over that box; afterwards
-// each covered tile pixel goes through the early-depth read and the global
-// atomic minimum once.  The minimum is associative and commutative, so this
+// are first combined by minimum in an LDS tile over that box (behind an
+// early-depth read of the tile entry); afterwards each covered tile pixel
+// goes into the global atomic minimum once.  The minimum is associative and commutative, so this
 // equals combining every point globally; it replaces one global round trip
 // per point by one per covered pixel.  Larger batches (close to the eye,
 // few points per pixel) combine every point globally.
@@ -86,140 +86,181 @@ __device__ __forceinline__ void decode(uint32_t lw, uint32_t mw, uint32_t hw, fl
 struct Loop {
   float P[3][3], t[3];
   uint32_t W, H;
-  uint32_t x0, y0, tw, th;  // tile rectangle (tiled batches)
+  uint32_t cx, cy;  // 0x4B000000 + tile origin (x0, y0): pixel_fast yields tile coordinates
+  uint32_t tw, th;  // tile rectangle size (tiled batches)
+  uint32_t tw8;     // tile row pitch in bytes
   uint64_t* vb;
 };
 
-// One point: true if it lands inside the image, with its pixel (px, py) and key.
-template <int CLS>
-__device__ __forceinline__ bool project(const Loop& L, float X, float Y, float Z, uint32_t idx, uint32_t& px,
-                                        uint32_t& py, uint64_t& key) {
-  const float hx = __builtin_fmaf(L.P[0][2], Z, __builtin_fmaf(L.P[0][1], Y, __builtin_fmaf(L.P[0][0], X, L.t[0])));
-  const float hy = __builtin_fmaf(L.P[1][2], Z, __builtin_fmaf(L.P[1][1], Y, __builtin_fmaf(L.P[1][0], X, L.t[1])));
-  const float hw = __builtin_fmaf(L.P[2][2], Z, __builtin_fmaf(L.P[2][1], Y, __builtin_fmaf(L.P[2][0], X, L.t[2])));
-  bool ok = true;
-  if constexpr (CLS != CLS_INSIDE) {
-    // hw > 0, 0 <= hx < W hw, 0 <= hy < H hw; the fma residuals carry the
-    // exact sign of hx - W hw (denormals are kept, so nothing underflows to 0).
-    ok = (hw > 0.0f) & (hx >= 0.0f) & (__builtin_fmaf(-(float)L.W, hw, hx) < 0.0f) & (hy >= 0.0f) &
-         (__builtin_fmaf(-(float)L.H, hw, hy) < 0.0f);
-  }
-  if constexpr (CLS == CLS_SLOW) {
-    // Exact floor of the real quotient: the binary64 quotient of two binary32
-    // values below 2^13 never crosses an integer.
-    px = (uint32_t)floor((double)hx / (double)hw);
-    py = (uint32_t)floor((double)hy / (double)hw);
-  } else {
-    // fma(hx, rcp(hw), 2^23) rounds the exact product to an integer n (the
-    // spacing of floats in [2^23, 2^24) is 1), |n - hx/hw| < 1/2 + 2^-9 for
-    // quotients below 2^13; the exactly signed residual hx - n hw then picks
-    // n or n - 1.  The integer is read from the float's bits.
-    const float r = __builtin_amdgcn_rcpf(hw);
-    const float tx = __builtin_fmaf(hx, r, 0x1p23f);
-    const float ty = __builtin_fmaf(hy, r, 0x1p23f);
-    const float ex = __builtin_fmaf(-(tx - 0x1p23f), hw, hx);
-    const float ey = __builtin_fmaf(-(ty - 0x1p23f), hw, hy);
-    px = __float_as_uint(tx) - (0x4B000000u + (ex < 0.0f ? 1u : 0u));
-    py = __float_as_uint(ty) - (0x4B000000u + (ey < 0.0f ? 1u : 0u));
-  }
-  // Never address outside the image, whatever the class proofs say.
-  ok = ok & (px < L.W) & (py < L.H);
-  key = ((uint64_t)__float_as_uint(hw) << 32) | (uint64_t)idx;
-  return ok;
+// Projection of one decoded point (the three fmaf chains, fixed order).
+struct Proj {
+  float hx, hy, hw;
+};
+__device__ __forceinline__ Proj project(const Loop& L, float X, float Y, float Z) {
+  Proj p;
+  p.hx = __builtin_fmaf(L.P[0][2], Z, __builtin_fmaf(L.P[0][1], Y, __builtin_fmaf(L.P[0][0], X, L.t[0])));
+  p.hy = __builtin_fmaf(L.P[1][2], Z, __builtin_fmaf(L.P[1][1], Y, __builtin_fmaf(L.P[1][0], X, L.t[1])));
+  p.hw = __builtin_fmaf(L.P[2][2], Z, __builtin_fmaf(L.P[2][1], Y, __builtin_fmaf(L.P[2][0], X, L.t[2])));
+  return p;
 }
 
-__device__ __forceinline__ void global_min(uint64_t* __restrict__ vb, uint32_t off, uint64_t key, uint32_t& natom) {
-  const uint64_t old = __hip_atomic_load(vb + off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-  if (key < old) {
-    __hip_atomic_fetch_min(vb + off, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    natom++;
-  }
+// hw > 0, 0 <= hx < W hw, 0 <= hy < H hw, exactly: the fma residuals carry the
+// exact sign of hx - W hw (denormals are kept, so nothing underflows to 0).
+__device__ __forceinline__ bool visible(const Loop& L, const Proj& p) {
+  return (p.hw > 0.0f) & (p.hx >= 0.0f) & (__builtin_fmaf(-(float)L.W, p.hw, p.hx) < 0.0f) & (p.hy >= 0.0f) &
+         (__builtin_fmaf(-(float)L.H, p.hw, p.hy) < 0.0f);
 }
+
+// floor(hx / hw) - x0 and floor(hy / hw) - y0 for quotients in [0, 2^13), hw
+// in [2^-60, 2^60]: fma(hx, rcp(hw), 2^23) rounds the exact product to an
+// integer n (the spacing of floats in [2^23, 2^24) is 1) with
+// |n - hx/hw| < 1/2 + 2^-9; the exactly signed residual hx - n hw picks n or
+// n - 1.  The integer is read from the float's bits (cx = 0x4B000000 + x0),
+// the correction is the borrow of the same subtraction.
+__device__ __forceinline__ void pixel_fast(const Proj& p, uint32_t cx, uint32_t cy, uint32_t& px, uint32_t& py) {
+  const float r = __builtin_amdgcn_rcpf(p.hw);
+  const float tx = __builtin_fmaf(p.hx, r, 0x1p23f);
+  const float ty = __builtin_fmaf(p.hy, r, 0x1p23f);
+  const float ex = __builtin_fmaf(-(tx - 0x1p23f), p.hw, p.hx);
+  const float ey = __builtin_fmaf(-(ty - 0x1p23f), p.hw, p.hy);
+  unsigned int bo;
+  px = __builtin_subc(__float_as_uint(tx), cx, (unsigned int)(ex < 0.0f), &bo);
+  py = __builtin_subc(__float_as_uint(ty), cy, (unsigned int)(ey < 0.0f), &bo);
+}
+
+// Exact floor of the real quotient for any class: the binary64 quotient of two
+// binary32 values below 2^13 never crosses an integer.
+__device__ __forceinline__ void pixel_exact(const Proj& p, uint32_t& px, uint32_t& py) {
+  px = (uint32_t)floor((double)p.hx / (double)p.hw);
+  py = (uint32_t)floor((double)p.hy / (double)p.hw);
+}
+
+__device__ __forceinline__ uint64_t make_key(float hw, uint32_t idx) {
+  return ((uint64_t)__float_as_uint(hw) << 32) | (uint64_t)idx;
+}
+
+struct Words {
+  uint4 l, m, h;
+};
 
 // Four consecutive points of one lane.
 template <int K, int CLS, bool TILED>
-__device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, uint4 lw, uint4 mw, uint4 hw, uint32_t i0,
+__device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const Words& w, uint32_t i0,
                                             uint32_t nvalid, uint32_t& natom) {
-  const uint32_t Lw[4] = {lw.x, lw.y, lw.z, lw.w};
-  const uint32_t Mw[4] = {mw.x, mw.y, mw.z, mw.w};
-  const uint32_t Hw[4] = {hw.x, hw.y, hw.z, hw.w};
-  uint32_t px[4], py[4];
-  uint64_t key[4];
-  bool ok[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    float X, Y, Z;
-    decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
-    ok[j] = project<CLS>(L, X, Y, Z, i0 + j, px[j], py[j], key[j]) && ((uint32_t)j < nvalid);
-  }
+  const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
+  const uint32_t Mw[4] = {w.m.x, w.m.y, w.m.z, w.m.w};
+  const uint32_t Hw[4] = {w.h.x, w.h.y, w.h.z, w.h.w};
   if constexpr (TILED) {
+    // Tile coordinates straight from the pixel computation.  The classify
+    // kernel tiles a batch only when it has proved that every point's pixel
+    // lies inside the tile rectangle.
+    // Early depth in LDS: the tile entry is read first and the 64-bit LDS
+    // atomic is issued only by a key that beats it (a stale read only costs
+    // an extra atomic: entries never increase).  Most points of a densely
+    // covered pixel lose this test, which removes most of the atomics and
+    // their same-address serialisation.
+    uint8_t* const tb = reinterpret_cast<uint8_t*>(tile);
+    uint32_t ad[4];
+    uint64_t key[4], old[4];
+    bool ok[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const uint32_t lx = px[j] - L.x0, ly = py[j] - L.y0;
-      if (ok[j] && lx < L.tw && ly < L.th) {
-        __hip_atomic_fetch_min(tile + (ly * L.tw + lx), key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      } else if (ok[j]) {  // outside the tile rectangle: never for a correct rectangle
-        global_min(L.vb, py[j] * L.W + px[j], key[j], natom);
-      }
+      float X, Y, Z;
+      decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
+      const Proj p = project(L, X, Y, Z);
+      ok[j] = (uint32_t)j < nvalid;
+      if constexpr (CLS != CLS_INSIDE) ok[j] = ok[j] && visible(L, p);
+      uint32_t lx, ly;
+      pixel_fast(p, L.cx, L.cy, lx, ly);
+      key[j] = make_key(p.hw, i0 + j);
+      ad[j] = __umul24(ly, L.tw8) + (lx << 3);
     }
-  } else {
-    // all early-depth reads first, then the atomics
-    uint64_t old[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       old[j] = 0;
-      if (ok[j]) old[j] = __hip_atomic_load(L.vb + (py[j] * L.W + px[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      if (ok[j])
+        old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (ok[j] && key[j] < old[j])
+        __hip_atomic_fetch_min(reinterpret_cast<uint64_t*>(tb + ad[j]), key[j], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    uint32_t off[4];
+    uint64_t key[4], old[4];
+    bool ok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float X, Y, Z;
+      decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
+      const Proj p = project(L, X, Y, Z);
+      ok[j] = (uint32_t)j < nvalid;
+      if constexpr (CLS != CLS_INSIDE) ok[j] = ok[j] && visible(L, p);
+      uint32_t px, py;
+      if constexpr (CLS == CLS_SLOW)
+        pixel_exact(p, px, py);
+      else
+        pixel_fast(p, L.cx, L.cy, px, py);
+      // Never address outside the image, whatever the class proofs say.
+      ok[j] = ok[j] && (px < L.W) && (py < L.H);
+      off[j] = __umul24(py, L.W) + px;
+      key[j] = make_key(p.hw, i0 + j);
+    }
+    // all early-depth reads first, then the atomics
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      old[j] = 0;
+      if (ok[j]) old[j] = __hip_atomic_load(L.vb + off[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (ok[j] && key[j] < old[j]) {
-        __hip_atomic_fetch_min(L.vb + (py[j] * L.W + px[j]), key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_min(L.vb + off[j], key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         natom++;
       }
     }
   }
 }
 
+template <int K>
+__device__ __forceinline__ Words load_group(const RenderArgs& a, uint32_t first, uint32_t g, uint32_t lane) {
+  const uint32_t q = first / 4 + g * 64 + lane;  // first is a multiple of 4
+  Words w;
+  w.l = reinterpret_cast<const uint4*>(a.low)[q];
+  if constexpr (K >= 20) w.m = reinterpret_cast<const uint4*>(a.med)[q];
+  else w.m = make_uint4(0, 0, 0, 0);
+  if constexpr (K == 30) w.h = reinterpret_cast<const uint4*>(a.high)[q];
+  else w.h = make_uint4(0, 0, 0, 0);
+  return w;
+}
+
 // The points of one batch, split over the workgroup's waves: wave w takes the
 // groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
-// 16-byte load per word, loads issued two groups ahead); wave 0 also takes
-// the ragged tail.
+// 16-byte load per word).  Two register sets alternate, each reloaded in place
+// right after use.  Wave 0 also takes the ragged tail.
 template <int K, int CLS, bool TILED>
 __device__ void raster_points(const Loop& L, const RenderArgs& a, uint64_t* tile, uint32_t first, uint32_t count,
                               uint32_t wave, uint32_t lane, uint32_t& natom) {
-  const uint4* __restrict__ L4 = reinterpret_cast<const uint4*>(a.low + first);
-  const uint4* __restrict__ M4 = reinterpret_cast<const uint4*>(a.med + first);
-  const uint4* __restrict__ H4 = reinterpret_cast<const uint4*>(a.high + first);
-  const uint4 z4 = make_uint4(0, 0, 0, 0);
   const uint32_t ngrp = count >> 8;
-  uint4 l0 = z4, m0 = z4, h0 = z4, l1 = z4, m1 = z4, h1 = z4;
-  if (wave < ngrp) {
-    const uint32_t q = wave * 64 + lane;
-    l0 = L4[q];
-    if constexpr (K >= 20) m0 = M4[q];
-    if constexpr (K == 30) h0 = H4[q];
-  }
-  if (wave + WAVES < ngrp) {
-    const uint32_t q = (wave + WAVES) * 64 + lane;
-    l1 = L4[q];
-    if constexpr (K >= 20) m1 = M4[q];
-    if constexpr (K == 30) h1 = H4[q];
-  }
-  for (uint32_t g = wave; g < ngrp; g += WAVES) {
-    uint4 l2 = z4, m2 = z4, h2 = z4;
-    if (g + 2 * WAVES < ngrp) {
-      const uint32_t q = (g + 2 * WAVES) * 64 + lane;
-      l2 = L4[q];
-      if constexpr (K >= 20) m2 = M4[q];
-      if constexpr (K == 30) h2 = H4[q];
+  const uint32_t nj = wave < ngrp ? (ngrp - wave + WAVES - 1) / WAVES : 0;  // this wave's groups
+  if (nj > 0) {
+    // Branch-free body: reloads are unconditional and clamped to the wave's
+    // last group, which is then simply processed again.  Combining a point
+    // twice by minimum changes nothing, and every wait counts exactly the
+    // loads in flight, so each load stays two groups ahead of its use.
+    const uint32_t glast = wave + (nj - 1) * WAVES;
+    uint32_t ga = wave, gb = min(wave + WAVES, glast);
+    Words A = load_group<K>(a, first, ga, lane);
+    Words B = load_group<K>(a, first, gb, lane);
+    for (uint32_t j = 0; j < nj; j += 2) {
+      four_points<K, CLS, TILED>(L, tile, A, first + ga * 256 + lane * 4, 4, natom);
+      ga = min(ga + 2 * WAVES, glast);
+      A = load_group<K>(a, first, ga, lane);
+      four_points<K, CLS, TILED>(L, tile, B, first + gb * 256 + lane * 4, 4, natom);
+      gb = min(gb + 2 * WAVES, glast);
+      B = load_group<K>(a, first, gb, lane);
     }
-    four_points<K, CLS, TILED>(L, tile, l0, m0, h0, first + g * 256 + lane * 4, 4, natom);
-    l0 = l1;
-    m0 = m1;
-    h0 = h1;
-    l1 = l2;
-    m1 = m2;
-    h1 = h2;
   }
   const uint32_t rem = count & 255u;
   if (rem && wave == 0) {  // ragged tail of the batch: scalar loads, per-point bounds
@@ -234,8 +275,11 @@ __device__ void raster_points(const Loop& L, const RenderArgs& a, uint64_t* tile
         if constexpr (K == 30) h[j] = a.high[first + j0 + j];
       }
     }
-    four_points<K, CLS, TILED>(L, tile, make_uint4(l[0], l[1], l[2], l[3]), make_uint4(m[0], m[1], m[2], m[3]),
-                               make_uint4(h[0], h[1], h[2], h[3]), first + j0, nv, natom);
+    Words t;
+    t.l = make_uint4(l[0], l[1], l[2], l[3]);
+    t.m = make_uint4(m[0], m[1], m[2], m[3]);
+    t.h = make_uint4(h[0], h[1], h[2], h[3]);
+    four_points<K, CLS, TILED>(L, tile, t, first + j0, nv, natom);
   }
 }
 
@@ -325,9 +369,19 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
       }
       const int cls = ins ? CLS_INSIDE : (safe ? CLS_PARTIAL : CLS_SLOW);
       // Tile rectangle: the projected corners' box, one pixel wider on each
-      // side, clipped to the image (front batches only).
+      // side, clipped to the image (front batches only).  Every point's pixel
+      // lies inside it when the binary32 evaluation (hx, hw off by at most
+      // M/16 each) moves its quotient by less than half a pixel:
+      //   (Mx + max|u| Mw) / 16 / (min_c hw - Mw) < 1/2, and likewise for y.
       uint32_t tiled = 0, x0 = 0, y0 = 0, tw = 0, th = 0;
-      if (front && cls != CLS_SLOW) {
+      double hwmin = H[2][0];
+#pragma unroll
+      for (int c = 1; c < 8; ++c) hwmin = fmin(hwmin, H[2][c]);
+      const double hwlo = hwmin - M[2];
+      const bool tight = front && hwlo > 0.0 &&
+                         M[0] + fmax(fabs(umin), fabs(umax)) * M[2] < 8.0 * hwlo &&
+                         M[1] + fmax(fabs(vmin), fabs(vmax)) * M[2] < 8.0 * hwlo;
+      if (tight && cls != CLS_SLOW) {
         const double fx0 = fmax(floor(fmax(umin, -4.0)) - 1.0, 0.0);
         const double fx1 = fmin(floor(fmin(umax, Wd + 4.0)) + 1.0, Wd - 1.0);
         const double fy0 = fmax(floor(fmax(vmin, -4.0)) - 1.0, 0.0);
@@ -423,6 +477,9 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
   while (i < nlive) {
+    // Take the next batch now; the atomic's latency hides behind this batch.
+    uint32_t grab = 0;
+    if (tid == 0) grab = atomicAdd(&a.hdr->work, 1u);
     const LiveBatch& rec = a.live[i];
     Loop L;
 #pragma unroll
@@ -436,12 +493,15 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
     L.vb = a.vb;
     const uint32_t mode = rec.mode, rxy = rec.rect_xy, rwh = rec.rect_wh;
     const uint32_t first = rec.first, count = rec.count;
-    L.x0 = rxy & 0xFFFFu;
-    L.y0 = rxy >> 16;
+    const uint32_t x0 = rxy & 0xFFFFu, y0 = rxy >> 16;
     L.tw = rwh & 0xFFFFu;
     L.th = rwh >> 16;
+    L.tw8 = L.tw * 8u;
     const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
     const bool tiled = (mode >> 16) & 1u;
+    // opaque to the optimiser, so that each biased constant stays one operand
+    L.cx = uni(0x4B000000u + (tiled ? x0 : 0u));
+    L.cy = uni(0x4B000000u + (tiled ? y0 : 0u));
     if (tiled) {
       if (k == 10) raster_by_class<10, true>(cls, L, a, tile, first, count, wave, lane, natom);
       else if (k == 20) raster_by_class<20, true>(cls, L, a, tile, first, count, wave, lane, natom);
@@ -452,17 +512,21 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
       else raster_by_class<30, false>(cls, L, a, tile, first, count, wave, lane, natom);
     }
     __syncthreads();  // the batch's points are all in the tile; s_next has been read
-    if (tid == 0) s_next = atomicAdd(&a.hdr->work, 1u);
+    if (tid == 0) s_next = grab;
     if (tiled) {
-      // Flush: every covered tile pixel once through early depth + global
-      // minimum, leaving the entry PR_EMPTY for the next batch.
+      // Flush: every covered tile pixel once into the global buffer, leaving
+      // the entry PR_EMPTY for the next batch.  Most covered pixels improve
+      // the global minimum, so the atomic is issued without a prior read
+      // (no round trip on this path).
       const uint32_t n = L.tw * L.th;
       for (uint32_t e = tid; e < n; e += THREADS) {
         const uint64_t v = tile[e];
         if (v != ~0ull) {
           tile[e] = ~0ull;
           const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
-          global_min(L.vb, (L.y0 + ly) * L.W + (L.x0 + lx), v, natom);
+          __hip_atomic_fetch_min(L.vb + ((y0 + ly) * L.W + (x0 + lx)), v, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+          natom++;
         }
       }
     }
