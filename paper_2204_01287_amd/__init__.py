@@ -13,6 +13,6 @@ Importing fails loudly if the library has not been built
 from ._binding import (  # noqa: F401
     PR_ADAPTIVE, PR_EMPTY, PR_FORCE10, PR_FORCE20, PR_FORCE30, PrError, Sizes, CloudBufs, RenderOpts, Stats,
     LIB_PATH, lib, pr_last_error, pr_create, pr_destroy, pr_cloud_sizes, pr_load_points, pr_build_batches,
-    pr_render, pr_resolve, pr_get_stats, pr_sync, pr_cloud_info, pr_cloud_free, EXPORTED,
+    pr_clear, pr_render, pr_resolve, pr_get_stats, pr_sync, pr_cloud_info, pr_cloud_free, EXPORTED,
     DeviceCloud, Context,
 )

@@ -22,7 +22,7 @@ _STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "
            -5: "PR_ENONFINITE", -6: "PR_ERANGE"}
 
 EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_load_points", "pr_build_batches",
-            "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free"]
+            "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free"]
 
 
 class PrError(RuntimeError):
@@ -45,11 +45,11 @@ class CloudBufs(ctypes.Structure):
 
 class RenderOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cull", ctypes.c_int32), ("t10", ctypes.c_float),
-                ("t20", ctypes.c_float), ("counters", ctypes.c_int32)]
+                ("t20", ctypes.c_float), ("counters", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
 
     @classmethod
-    def make(cls, precision=PR_ADAPTIVE, cull=1, t10=500.0, t20=512000.0, counters=0):
-        return cls(precision, cull, t10, t20, counters)
+    def make(cls, precision=PR_ADAPTIVE, cull=1, t10=500.0, t20=512000.0, counters=0, accumulate=0):
+        return cls(precision, cull, t10, t20, counters, accumulate)
 
 
 class Stats(ctypes.Structure):
@@ -72,6 +72,7 @@ lib.pr_destroy.restype = None
 lib.pr_cloud_sizes.argtypes = [_U64, _U32, _I, ctypes.POINTER(Sizes)]
 lib.pr_load_points.argtypes = [_P, _P, _P, _U64, _I, ctypes.POINTER(CloudBufs), ctypes.POINTER(_P)]
 lib.pr_build_batches.argtypes = [_P, _P, _U32, _I]
+lib.pr_clear.argtypes = [_P, _P, _U32, _U32]
 lib.pr_render.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts), _P]
 lib.pr_resolve.argtypes = [_P, _P, _P, _U32, _U32, _U32, _P]
 lib.pr_get_stats.argtypes = [_P, ctypes.POINTER(Stats)]
@@ -79,7 +80,7 @@ lib.pr_sync.argtypes = [_P]
 lib.pr_cloud_info.argtypes = [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U32)]
 lib.pr_cloud_free.argtypes = [_P]
 lib.pr_cloud_free.restype = None
-for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_render", "pr_resolve",
+for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
            "pr_get_stats", "pr_sync", "pr_cloud_info"):
     getattr(lib, _f).restype = ctypes.c_int
 
@@ -139,6 +140,10 @@ def pr_load_points(ctx, xyz, rgba, n: int, src_on_device: bool, bufs: CloudBufs)
 
 def pr_build_batches(ctx, cloud, batch_size: int, morton: bool):
     _check(lib.pr_build_batches(ctx, cloud, batch_size, int(morton)), "pr_build_batches")
+
+
+def pr_clear(ctx, visbuf, w: int, h: int):
+    _check(lib.pr_clear(ctx, _ptr(visbuf), w, h), "pr_clear")
 
 
 def pr_render(ctx, cloud, view, proj, w: int, h: int, opts: RenderOpts | None, visbuf):

@@ -32,13 +32,17 @@ struct LiveBatch {
 };
 static_assert(sizeof(LiveBatch) == 80, "live batch record is 80 bytes");
 
-// Per-frame counters of the render path (in the cloud's scratch area).
+// Per-frame counters of the render path (in the cloud's scratch area).  The
+// live batches are handed out through RENDER_QUEUES work queues (queue q
+// owns live batches q, q + RENDER_QUEUES, ...), each counter on its own
+// 128-byte line: one shared counter serialises every workgroup's request.
+constexpr uint32_t RENDER_QUEUES = 8;
 struct FrameHeader {
   uint32_t live_count;  // live batches written by classify
-  uint32_t work;        // next live batch to hand out (render work queue)
-  uint32_t pad[62];
+  uint32_t pad[31];
+  uint32_t queue[RENDER_QUEUES][32];  // queue[q][0]: next position of queue q
 };
-static_assert(sizeof(FrameHeader) == 256, "frame header is 256 bytes");
+static_assert(sizeof(FrameHeader) == 128 * (1 + RENDER_QUEUES), "frame header layout");
 
 inline uint64_t frame_area_bytes(uint64_t nb) { return sizeof(FrameHeader) + sizeof(LiveBatch) * nb; }
 

@@ -46,6 +46,11 @@ constexpr int CLS_INSIDE = 0, CLS_PARTIAL = 1, CLS_SLOW = 2;
 constexpr int WAVES = 4;
 constexpr int THREADS = 64 * WAVES;
 constexpr uint32_t TILE_MAX = 4096;  // 32 KiB of 64-bit keys
+// Point loads in flight per wave (groups of 256 points); 10,240-point batches
+// give each of the four waves exactly ten groups.
+#ifndef PREFETCH
+#define PREFETCH 5
+#endif
 
 // ------------------------------------------------------------------ clear
 // Fills the visibility buffer with all-ones (PR_EMPTY), resets the frame's
@@ -59,7 +64,8 @@ __global__ void __launch_bounds__(256) k_clear(uint4* __restrict__ vb4, uint64_t
   for (uint64_t i = tid; i < n4; i += stride) vb4[i] = ones;
   if (tid == 0 && (npix & 1)) vb[npix - 1] = ~0ull;
   if (blockIdx.x == 0) {
-    if (hdr && threadIdx.x < 2) (&hdr->live_count)[threadIdx.x] = 0;
+    if (hdr && threadIdx.x == 0) hdr->live_count = 0;
+    if (hdr && threadIdx.x < RENDER_QUEUES) hdr->queue[threadIdx.x][0] = 0;
     if (reset_stats && threadIdx.x < 16) dev->stats[threadIdx.x] = 0;
   }
 }
@@ -237,29 +243,36 @@ __device__ __forceinline__ Words load_group(const RenderArgs& a, uint32_t first,
 
 // The points of one batch, split over the workgroup's waves: wave w takes the
 // groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
-// 16-byte load per word).  Two register sets alternate, each reloaded in place
-// right after use.  Wave 0 also takes the ragged tail.
+// 16-byte load per word).  Wave 0 also takes the ragged tail.
 template <int K, int CLS, bool TILED>
 __device__ void raster_points(const Loop& L, const RenderArgs& a, uint64_t* tile, uint32_t first, uint32_t count,
                               uint32_t wave, uint32_t lane, uint32_t& natom) {
   const uint32_t ngrp = count >> 8;
   const uint32_t nj = wave < ngrp ? (ngrp - wave + WAVES - 1) / WAVES : 0;  // this wave's groups
   if (nj > 0) {
-    // Branch-free body: reloads are unconditional and clamped to the wave's
-    // last group, which is then simply processed again.  Combining a point
-    // twice by minimum changes nothing, and every wait counts exactly the
-    // loads in flight, so each load stays two groups ahead of its use.
+    // PREFETCH register sets rotate through the wave's groups; each is
+    // reloaded in place right after use, so every load is issued PREFETCH
+    // groups ahead of its use.  The body is branch-free: reloads are
+    // unconditional and clamped to the wave's last group, and a group
+    // index past the end repeats the last group with no valid points.
+    // Every wait then counts exactly the loads in flight.
     const uint32_t glast = wave + (nj - 1) * WAVES;
-    uint32_t ga = wave, gb = min(wave + WAVES, glast);
-    Words A = load_group<K>(a, first, ga, lane);
-    Words B = load_group<K>(a, first, gb, lane);
-    for (uint32_t j = 0; j < nj; j += 2) {
-      four_points<K, CLS, TILED>(L, tile, A, first + ga * 256 + lane * 4, 4, natom);
-      ga = min(ga + 2 * WAVES, glast);
-      A = load_group<K>(a, first, ga, lane);
-      four_points<K, CLS, TILED>(L, tile, B, first + gb * 256 + lane * 4, 4, natom);
-      gb = min(gb + 2 * WAVES, glast);
-      B = load_group<K>(a, first, gb, lane);
+    Words R[PREFETCH];
+    uint32_t gi[PREFETCH];
+#pragma unroll
+    for (int d = 0; d < PREFETCH; ++d) {
+      gi[d] = wave + d * WAVES;
+      R[d] = load_group<K>(a, first, min(gi[d], glast), lane);
+    }
+    for (uint32_t j = 0; j < nj; j += PREFETCH) {
+#pragma unroll
+      for (int d = 0; d < PREFETCH; ++d) {
+        const uint32_t g = gi[d];
+        four_points<K, CLS, TILED>(L, tile, R[d], first + min(g, glast) * 256 + lane * 4, g <= glast ? 4u : 0u,
+                                   natom);
+        gi[d] = g + PREFETCH * WAVES;
+        R[d] = load_group<K>(a, first, min(gi[d], glast), lane);
+      }
     }
   }
   const uint32_t rem = count & 255u;
@@ -460,7 +473,7 @@ __device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const Re
     raster_points<K, CLS_SLOW, false>(L, a, tile, first, count, wave, lane, natom);
 }
 
-// Persistent: each workgroup takes live batches from the work queue until it
+// Persistent: each workgroup takes live batches from its work queue until it
 // is empty.  The LDS tile is all PR_EMPTY between batches (the flush resets
 // what it reads), so a batch needs two barriers: one after its points, one
 // after its flush.
@@ -471,7 +484,10 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
   for (uint32_t e = tid; e < TILE_MAX / 2; e += THREADS) reinterpret_cast<uint4*>(tile)[e] = ones;
-  if (tid == 0) s_next = atomicAdd(&a.hdr->work, 1u);
+  // this workgroup's queue: workgroups are spread over the queues round-robin
+  const uint32_t q = blockIdx.x % RENDER_QUEUES;
+  uint32_t* const qc = &a.hdr->queue[q][0];
+  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
   const uint32_t nlive = a.hdr->live_count;
   __syncthreads();
   uint32_t i = uni(s_next);
@@ -479,7 +495,7 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
   while (i < nlive) {
     // Take the next batch now; the atomic's latency hides behind this batch.
     uint32_t grab = 0;
-    if (tid == 0) grab = atomicAdd(&a.hdr->work, 1u);
+    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
     const LiveBatch& rec = a.live[i];
     Loop L;
 #pragma unroll
