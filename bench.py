@@ -56,8 +56,17 @@ def workload(name: str, n_override: int | None):
     raise SystemExit(f"unknown workload {name}")
 
 
-def load_cloud(ctx, wl, chunk=64_000_000):
-    """Generate the cloud on the host in chunks (pinned, double-buffered) and stream it to HBM."""
+def _wait(pending):
+    if pending is not None and hasattr(pending, "result"):
+        pending.result()
+
+
+def load_cloud(ctx, wl, chunk=64_000_000, on_chunk=None):
+    """Generate the cloud on the host in chunks (pinned, double-buffered) and stream it to HBM.
+
+    on_chunk(lo, hi, xyz, rgba), if given, sees every generated chunk (numpy views of points [lo, hi) in input
+    order) before it is uploaded; if it returns an object with .result(), that is waited for before the chunk's
+    host buffer is reused."""
     import numpy as np
     import torch
     import paper_2204_01287_amd as pr
@@ -71,10 +80,14 @@ def load_cloud(ctx, wl, chunk=64_000_000):
     t0 = time.perf_counter()
     if wl["name"].startswith("primitives"):
         xyz, rgba = synth.primitives(wl["seed"], n)
+        if on_chunk:
+            _wait(on_chunk(0, n, xyz, rgba))
         mem["xyz"][: 12 * n].copy_(torch.from_numpy(xyz.view(np.uint8).reshape(-1)))
         mem["rgba"][: 4 * n].copy_(torch.from_numpy(rgba.view(np.uint8)))
     elif wl["order"] == 1:
         xyz, rgba = synth.terrain(wl["seed"], n, order=1)
+        if on_chunk:
+            _wait(on_chunk(0, n, xyz, rgba))
         mem["xyz"][: 12 * n].copy_(torch.from_numpy(xyz.view(np.uint8).reshape(-1)))
         mem["rgba"][: 4 * n].copy_(torch.from_numpy(rgba.view(np.uint8)))
         del xyz, rgba
@@ -83,13 +96,18 @@ def load_cloud(ctx, wl, chunk=64_000_000):
         host = [(torch.empty(12 * chunk, dtype=torch.uint8, pin_memory=True),
                  torch.empty(4 * chunk, dtype=torch.uint8, pin_memory=True)) for _ in range(2)]
         done = [None, None]
+        seen = [None, None]
         side = torch.cuda.Stream(dev)
         for ci, lo in enumerate(range(0, n, chunk)):
             hi = min(lo + chunk, n)
             hx, hc = host[ci % 2]
             if done[ci % 2] is not None:
                 done[ci % 2].synchronize()
+            _wait(seen[ci % 2])
             synth.terrain_range(wl["seed"], n, lo, hi, hx.data_ptr(), hc.data_ptr())
+            if on_chunk:
+                seen[ci % 2] = on_chunk(lo, hi, hx[: 12 * (hi - lo)].numpy().view(np.float32).reshape(-1, 3),
+                                        hc[: 4 * (hi - lo)].numpy().view(np.uint32))
             with torch.cuda.stream(side):
                 mem["xyz"][12 * lo: 12 * hi].copy_(hx[: 12 * (hi - lo)], non_blocking=True)
                 mem["rgba"][4 * lo: 4 * hi].copy_(hc[: 4 * (hi - lo)], non_blocking=True)
@@ -99,6 +117,8 @@ def load_cloud(ctx, wl, chunk=64_000_000):
             if ci % 8 == 0:
                 log(f"generated {hi / 1e6:.0f}M / {n / 1e6:.0f}M points ({time.perf_counter() - t0:.1f} s)")
         side.synchronize()
+        for w in seen:
+            _wait(w)
         del host
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0

@@ -47,6 +47,9 @@ def _load():
         lib.synth_terrain_range.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.synth_terrain_range.restype = ctypes.c_int
+        lib.synth_terrain_gather.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64,
+                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.synth_terrain_gather.restype = ctypes.c_int
         lib.synth_terrain_height.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double]
         lib.synth_terrain_height.restype = ctypes.c_double
         _lib = lib
@@ -89,6 +92,18 @@ def terrain_range(seed: int, n: int, lo: int, hi: int, xyz_ptr: int, rgba_ptr: i
     rc = _load().synth_terrain_range(seed, n, lo, hi, sigma, xyz_ptr, rgba_ptr, threads)
     if rc != 0:
         raise RuntimeError(f"synth_terrain_range failed ({rc})")
+
+
+def terrain_gather(seed: int, n: int, idx, sigma: float = 0.01, threads: int = 0):
+    """Points idx[j] (uint32, each < n) of the index-order terrain of n points, in the order of idx."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    xyz = np.empty((idx.shape[0], 3), dtype=np.float32)
+    rgba = np.empty(idx.shape[0], dtype=np.uint32)
+    rc = _load().synth_terrain_gather(seed, n, idx.ctypes.data, idx.shape[0], sigma, xyz.ctypes.data,
+                                      rgba.ctypes.data, threads)
+    if rc != 0:
+        raise RuntimeError(f"synth_terrain_gather failed ({rc})")
+    return xyz, rgba
 
 
 def terrain_height(seed: int, x: float, y: float) -> float:

@@ -238,6 +238,7 @@ typedef struct {
   float* xyz;
   uint32_t* rgba;
   uint16_t* tile; /* optional: serpentine tile id per point */
+  const uint32_t* idx; /* gather: point indices, output slot j holds point idx[j] */
 } terrain_job;
 
 static void make_scene(uint64_t seed, building_t* B, pole_t* Q) {
@@ -273,9 +274,10 @@ static inline uint16_t serpentine_tile(double x, double y) {
   return (uint16_t)(ty * 100 + ((ty & 1) ? 99 - tx : tx));
 }
 
-static void terrain_range(void* arg, uint64_t lo, uint64_t hi) {
-  terrain_job* J = (terrain_job*)arg;
-  for (uint64_t i = lo; i < hi; ++i) {
+/* Point i of the index-order terrain cloud: position f[3] and colour c; the
+ * serpentine tile is written to J->tile[i] when requested. */
+static void terrain_point(const terrain_job* J, uint64_t i, float f[3], uint32_t* c) {
+  {
     uint64_t base = i * CTR_PER_POINT;
     double pos[3];
     if (i < J->n_ground) {
@@ -306,10 +308,19 @@ static void terrain_range(void* arg, uint64_t lo, uint64_t hi) {
     double g[4];
     box_muller(sm_at(J->seed, base + 16), sm_at(J->seed, base + 17), &g[0], &g[1]);
     box_muller(sm_at(J->seed, base + 18), sm_at(J->seed, base + 19), &g[2], &g[3]);
-    float f[3];
     for (int a = 0; a < 3; ++a) f[a] = (float)(pos[a] + J->sigma * g[a]);
+    *c = (uint32_t)(sm_at(J->seed, base + 20) >> 32);
+  }
+}
+
+static void terrain_range(void* arg, uint64_t lo, uint64_t hi) {
+  terrain_job* J = (terrain_job*)arg;
+  for (uint64_t i = lo; i < hi; ++i) {
+    float f[3];
+    uint32_t c;
+    terrain_point(J, i, f, &c);
     J->xyz[3 * i] = f[0]; J->xyz[3 * i + 1] = f[1]; J->xyz[3 * i + 2] = f[2];
-    J->rgba[i] = (uint32_t)(sm_at(J->seed, base + 20) >> 32);
+    J->rgba[i] = c;
     if (J->tile) J->tile[i] = serpentine_tile(f[0], f[1]);
   }
 }
@@ -375,6 +386,52 @@ int synth_terrain_range(uint64_t seed, uint64_t n, uint64_t lo, uint64_t hi, dou
     jobs[k].fn = terrain_range; jobs[k].arg = &J;
     jobs[k].lo = lo + cnt * (uint64_t)k / (uint64_t)t;
     jobs[k].hi = lo + cnt * (uint64_t)(k + 1) / (uint64_t)t;
+  }
+  for (int k = 1; k < t; ++k) pthread_create(&th[k], NULL, range_thread, &jobs[k]);
+  range_thread(&jobs[0]);
+  for (int k = 1; k < t; ++k) pthread_join(th[k], NULL);
+  free(J.B); free(J.Q);
+  return 0;
+}
+
+static void terrain_gather(void* arg, uint64_t lo, uint64_t hi) {
+  terrain_job* J = (terrain_job*)arg;
+  for (uint64_t j = lo; j < hi; ++j) {
+    float f[3];
+    uint32_t c;
+    terrain_point(J, J->idx[j], f, &c);
+    J->xyz[3 * j] = f[0]; J->xyz[3 * j + 1] = f[1]; J->xyz[3 * j + 2] = f[2];
+    J->rgba[j] = c;
+  }
+}
+
+/* Points idx[0 .. count) of the index-order terrain cloud of n points (each
+ * index < n), written to xyz[3j ..] and rgba[j]: the same bytes as those
+ * points of synth_terrain(order = 0).  Returns 0, -1 on bad arguments, -2 if
+ * temporary memory is unavailable. */
+int synth_terrain_gather(uint64_t seed, uint64_t n, const uint32_t* idx, uint64_t count, double sigma,
+                         float* xyz, uint32_t* rgba, int nthreads) {
+  if ((count && (!idx || !xyz || !rgba))) return -1;
+  for (uint64_t j = 0; j < count; ++j)
+    if ((uint64_t)idx[j] >= n) return -1;
+  terrain_job J;
+  memset(&J, 0, sizeof J);
+  J.seed = seed; J.n = n; J.sigma = sigma;
+  J.n_ground = (uint64_t)((double)n * 0.80);
+  J.n_build = (uint64_t)((double)n * 0.96);
+  J.B = (building_t*)malloc(sizeof(building_t) * N_BUILDINGS);
+  J.Q = (pole_t*)malloc(sizeof(pole_t) * N_POLES);
+  if (!J.B || !J.Q) { free(J.B); free(J.Q); return -2; }
+  make_scene(seed, J.B, J.Q);
+  J.xyz = xyz; J.rgba = rgba; J.idx = idx;
+  range_job jobs[256];
+  pthread_t th[256];
+  int t = pick_threads(nthreads);
+  if ((uint64_t)t > count) t = count ? (int)count : 1;
+  for (int k = 0; k < t; ++k) {
+    jobs[k].fn = terrain_gather; jobs[k].arg = &J;
+    jobs[k].lo = count * (uint64_t)k / (uint64_t)t;
+    jobs[k].hi = count * (uint64_t)(k + 1) / (uint64_t)t;
   }
   for (int k = 1; k < t; ++k) pthread_create(&th[k], NULL, range_thread, &jobs[k]);
   range_thread(&jobs[0]);

@@ -1,0 +1,278 @@
+"""Parity at the full workload sizes, in the launch configuration that bench.py times.
+
+Every GPU frame here is bench.py's: pr_clear, then pr_render with accumulate = 1, then pr_resolve with the
+clear colour 0xFF000000, on the context's stream, with the persistent render grid of pr_create.
+
+C2 -- 100,000,000-point terrain (serpentine generation order, Morton build), orbit frames 0/15/30/45 at 1920x1080.
+The oracle builds and renders the same cloud.  The whole build (positions in render order, colours, permutation,
+batch records, low/med/high words), every visibility buffer, every framebuffer and the frame counters are compared
+element by element.
+
+C3 -- 2,000,000,000-point terrain (index generation order, Morton build), stereo pair 2 x 2016 x 2240.  The oracle
+cannot sort 2e9 points in test time, so the device's Morton permutation is checked by the two properties that make
+it unique:
+  * it is a permutation of 0..n-1;
+  * the oracle's Morton codes of the generator's points taken in that order (over the oracle's box of the
+    generator's cloud) are non-decreasing, with equal codes in increasing input index.
+A stable sort by code is the only order with both.  Everything else compared is the oracle's, computed from the
+generator's points in that order: batch table, Eq. 1 words, colours, per-batch decisions and frame counters, and
+the complete visibility buffer and framebuffer of each eye.  The oracle renders interleaved batch sets on worker
+threads into private buffers that are merged by elementwise minimum; the minimum is associative and commutative,
+so the merge is exact.
+"""
+from __future__ import annotations
+
+import time
+import types
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_vb_equal, oracle_stats_match, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+S = 10240
+CLEAR = 0xFF000000
+CH = 64_000_000  # host chunk: 6250 whole batches
+WORKERS = 4      # build-check workers, each generator call on 4 threads: 16 host threads, the GPU host's share
+RENDER_WORKERS = 16
+
+
+def _t():
+    return time.perf_counter()
+
+
+def _u32(t):
+    """A torch int32 tensor (device) as a host numpy uint32 array."""
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2204_01287_amd as pr
+
+    assert torch.cuda.is_available()
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+def _views(cloud, n, nb):
+    import torch
+
+    m = cloud["mem"]
+    return types.SimpleNamespace(
+        xyz=m["xyz"][: 12 * n].view(torch.int32), perm=m["perm"][: 4 * n].view(torch.int32),
+        colors=m["colors"][: 4 * n].view(torch.int32), low=m["low"][: 4 * n].view(torch.int32),
+        med=m["med"][: 4 * n].view(torch.int32), high=m["high"][: 4 * n].view(torch.int32),
+        batches=m["batches"][: 32 * nb])
+
+
+def _bench_frame(ctx, handle, cam):
+    """One eye exactly as bench.py times it; returns host copies of VB and FB and the frame counters."""
+    import torch
+    import paper_2204_01287_amd as pr
+
+    dev = torch.device("cuda", 0)
+    vb = torch.empty(cam.width * cam.height, dtype=torch.int64, device=dev)
+    fb = torch.empty(cam.width * cam.height, dtype=torch.int32, device=dev)
+    pr.pr_clear(ctx.handle, vb, cam.width, cam.height)
+    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height, pr.RenderOpts.make(accumulate=1), vb)
+    pr.pr_resolve(ctx.handle, handle, vb, cam.width, cam.height, CLEAR, fb)
+    pr.pr_sync(ctx.handle)
+    out_vb, out_fb = vb.cpu().numpy().view(np.uint64), fb.cpu().numpy().view(np.uint32)
+    # the counters frame (bench.py's untimed first frame)
+    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height, pr.RenderOpts.make(counters=1), vb)
+    st = pr.pr_get_stats(ctx.handle)
+    assert np.array_equal(vb.cpu().numpy().view(np.uint64), out_vb), "counters frame differs from the timed frame"
+    return out_vb, out_fb, st
+
+
+def _oracle_frame(built, cam, nb):
+    """The oracle over every batch, on worker threads (interleaved batch sets, private buffers, min-merge)."""
+    groups = [np.arange(g, nb, 4 * RENDER_WORKERS, dtype=np.uint64) for g in range(min(nb, 4 * RENDER_WORKERS))]
+
+    def job(ids):
+        return oracle.render(built, cam.view, cam.proj, cam.width, cam.height, batch_ids=ids)
+
+    vb, st = None, None
+    with ThreadPoolExecutor(RENDER_WORKERS) as ex:
+        for v, s in ex.map(job, groups):
+            vb = v if vb is None else np.minimum(vb, v)
+            if st is None:
+                st = s
+            else:
+                for k in ("batches", "culled", "points"):
+                    st[k] += s[k]
+                for k in ("level_batches", "level_points"):
+                    st[k] = [a + b for a, b in zip(st[k], s[k])]
+    return vb, st
+
+
+def _check_eye(ctx, handle, built, colors, cam, nb, tag):
+    t0 = _t()
+    say(f"{tag}: bench frame on the GPU ({cam.width}x{cam.height})")
+    vb, fb, st = _bench_frame(ctx, handle, cam)
+    say(f"{tag}: GPU frame done ({_t() - t0:.1f} s); oracle render of {nb} batches on {RENDER_WORKERS} threads")
+    ref, st_ref = _oracle_frame(built, cam, nb)
+    say(f"{tag}: oracle done ({_t() - t0:.1f} s): {st_ref}")
+    assert_vb_equal(vb, ref, cam.width)
+    assert np.array_equal(fb, oracle.resolve(ref, colors, CLEAR)), "framebuffer differs"
+    oracle_stats_match(st, st_ref)
+    assert st["points"] > 0 and np.count_nonzero(ref != oracle.EMPTY) > 0
+
+
+# =================================================================== C2: 1e8
+@pytest.fixture(scope="module")
+def c2(ctx):
+    import torch
+    import bench
+
+    wl = bench.workload("c2", None)
+    seen = {}
+
+    def keep(lo, hi, xyz, rgba):
+        seen["xyz"], seen["rgba"] = xyz, rgba
+
+    say(f"C2: generate and build {wl['n']} points on the GPU")
+    cloud = bench.load_cloud(ctx, wl, on_chunk=keep)
+    t0 = _t()
+    say("C2: oracle build (Morton sort, batches, Eq. 1) of the same points")
+    B = oracle.build_cloud(seen["xyz"], seen["rgba"], S, morton=True)
+    say(f"C2: oracle build done ({_t() - t0:.1f} s)")
+    yield types.SimpleNamespace(wl=wl, cloud=cloud, B=B, n=wl["n"], nb=cloud["nb"])
+    import paper_2204_01287_amd as pr
+
+    pr.pr_cloud_free(cloud["handle"])
+    cloud.clear()
+    torch.cuda.empty_cache()
+
+
+def test_c2_build_full(c2):
+    n, nb, B = c2.n, c2.nb, c2.B
+    assert nb == B.batches.shape[0]
+    v = _views(c2.cloud, n, nb)
+    say("C2: compare every build output with the oracle")
+    for f in ("perm", "colors", "low", "med", "high"):
+        a = _u32(getattr(v, f))
+        b = getattr(B, f)
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"{f}: {len(bad)} mismatches, first at {bad[:5]}")
+    assert np.array_equal(_u32(v.xyz), B.xyz.view(np.uint32).reshape(-1)), "positions in render order differ"
+    assert np.array_equal(v.batches.cpu().numpy(), B.batches.view(np.uint8)), "batch records differ"
+
+
+@pytest.mark.parametrize("frame", [0, 1, 2, 3])
+def test_c2_orbit_frame(ctx, c2, frame):
+    cam = c2.wl["cams"][frame]
+    _check_eye(ctx, c2.cloud["handle"], c2.B, c2.B.colors, cam, c2.nb, f"C2 orbit view {frame}")
+
+
+# =================================================================== C3: 2e9
+def _c3_oracle_side(ns):
+    """Check the device's Morton build against the oracle over all 2e9 points; keep the oracle's build."""
+    import torch
+
+    n, nb, seed = ns.n, ns.nb, ns.wl["seed"]
+    v = _views(ns.cloud, n, nb)
+    t0 = _t()
+    # 1. perm is a permutation of 0..n-1 (bounds first: an out-of-range index must not reach the GPU)
+    say("C3: permutation check on the device")
+    marks = torch.zeros(n, dtype=torch.uint8, device=v.perm.device)
+    for lo in range(0, n, CH):
+        idx = v.perm[lo:min(n, lo + CH)].to(torch.int64) & 0xFFFFFFFF
+        assert int(idx.max()) < n, "perm holds an index >= n"
+        marks[idx] = 1
+    assert int(marks.min()) == 1, "perm is not a permutation"
+    del marks, idx
+    torch.cuda.synchronize()
+    say(f"C3: permutation ok ({_t() - t0:.1f} s); chunked pass over the build")
+    # 2. chunked pass: generator points in device order -> oracle codes, batches, words; compare
+    cmin, cmax = ns.cloud_box
+    built = types.SimpleNamespace(batches=np.empty(nb, oracle.BATCH_DTYPE), low=np.empty(n, np.uint32),
+                                  med=np.empty(n, np.uint32), high=np.empty(n, np.uint32))
+    colors = np.empty(n, np.uint32)
+    gb_all = v.batches.cpu().numpy()
+
+    def job(lo):
+        hi = min(n, lo + CH)
+        perm = _u32(v.perm[lo:hi])
+        ox, oc = synth.terrain_gather(seed, n, perm, threads=4)
+        codes = oracle.morton_codes(ox, cmin, cmax)
+        tie = codes[1:] == codes[:-1]
+        r = dict(lo=lo, mono=bool(np.all(codes[1:] >= codes[:-1])), stable=bool(np.all(perm[1:][tie] > perm[:-1][tie])),
+                 head=(int(codes[0]), int(perm[0])), tail=(int(codes[-1]), int(perm[-1])))
+        r["xyz"] = bool(np.array_equal(_u32(v.xyz[3 * lo:3 * hi]), ox.view(np.uint32).reshape(-1)))
+        r["colors"] = bool(np.array_equal(_u32(v.colors[lo:hi]), oc))
+        ob = oracle.make_batches(ox, S)
+        words = oracle.quantize(ox, ob)
+        for f, w in zip(("low", "med", "high"), words):
+            r[f] = bool(np.array_equal(_u32(getattr(v, f)[lo:hi]), w))
+            getattr(built, f)[lo:hi] = w
+        ob["first"] += np.uint32(lo)
+        b0 = lo // S
+        r["batches"] = bool(np.array_equal(gb_all[32 * b0:32 * (b0 + len(ob))], ob.view(np.uint8)))
+        built.batches[b0:b0 + len(ob)] = ob
+        colors[lo:hi] = oc
+        return r
+
+    with ThreadPoolExecutor(WORKERS) as ex:
+        res = []
+        for r in ex.map(job, range(0, n, CH)):
+            res.append(r)
+            if len(res) % 8 == 0:
+                say(f"C3: {len(res)} chunks checked ({_t() - t0:.1f} s)")
+    say(f"C3: chunked pass done ({_t() - t0:.1f} s)")
+    return res, built, colors
+
+
+@pytest.fixture(scope="module")
+def c3(ctx):
+    import torch
+    import bench
+
+    wl = bench.workload("c3", None)
+    boxes = []
+    pool = ThreadPoolExecutor(2)
+
+    def box(lo, hi, xyz, rgba):
+        f = pool.submit(oracle.cloud_aabb, xyz)
+        boxes.append(f)
+        return f
+
+    say(f"C3: generate and build {wl['n']} points on the GPU")
+    cloud = bench.load_cloud(ctx, wl, on_chunk=box)
+    pool.shutdown()
+    corners = np.array([c for f in boxes for c in f.result()], np.float32)
+    ns = types.SimpleNamespace(wl=wl, cloud=cloud, n=wl["n"], nb=cloud["nb"], cloud_box=oracle.cloud_aabb(corners))
+    ns.res, ns.built, ns.colors = _c3_oracle_side(ns)
+    yield ns
+    import paper_2204_01287_amd as pr
+
+    pr.pr_cloud_free(cloud["handle"])
+    cloud.clear()
+    torch.cuda.empty_cache()
+
+
+def test_c3_build_full(c3):
+    res = sorted(c3.res, key=lambda r: r["lo"])
+    assert sum(1 for _ in range(0, c3.n, CH)) == len(res)
+    for r in res:
+        for k in ("mono", "stable", "xyz", "colors", "low", "med", "high", "batches"):
+            assert r[k], f"chunk at {r['lo']}: {k} check failed"
+    for a, b in zip(res, res[1:]):  # across chunk seams
+        assert a["tail"][0] <= b["head"][0], f"Morton order broken at {b['lo']}"
+        if a["tail"][0] == b["head"][0]:
+            assert a["tail"][1] < b["head"][1], f"stability broken at {b['lo']}"
+
+
+@pytest.mark.parametrize("eye", [0, 1])
+def test_c3_stereo_eye(ctx, c3, eye):
+    cam = c3.wl["cams"][eye]
+    _check_eye(ctx, c3.cloud["handle"], c3.built, c3.colors, cam, c3.nb, f"C3 eye {eye}")

@@ -1,5 +1,6 @@
 """The seeded generators: deterministic per (seed, index), independent of threading."""
 import numpy as np
+import pytest
 
 import synth
 
@@ -49,3 +50,15 @@ def test_terrain_range_matches_whole_cloud():
         c = np.empty(hi - lo, np.uint32)
         synth.terrain_range(6, n, lo, hi, x.ctypes.data, c.ctypes.data, threads=3)
         assert np.array_equal(x, xyz[lo:hi]) and np.array_equal(c, rgba[lo:hi])
+
+
+def test_terrain_gather_matches_whole_cloud():
+    n = 123_457
+    xyz, rgba = synth.terrain(6, n, order=0)
+    idx = np.random.default_rng(0).integers(0, n, 5000).astype(np.uint32)
+    idx[:3] = (0, n - 1, 0)
+    for t in (1, 5):
+        x, c = synth.terrain_gather(6, n, idx, threads=t)
+        assert np.array_equal(x, xyz[idx]) and np.array_equal(c, rgba[idx])
+    with pytest.raises(RuntimeError):
+        synth.terrain_gather(6, n, np.array([n], np.uint32))
