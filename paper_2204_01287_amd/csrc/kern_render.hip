@@ -92,7 +92,7 @@ __device__ __forceinline__ void decode(uint32_t lw, uint32_t mw, uint32_t hw, fl
 struct Loop {
   float P[3][3], t[3];
   uint32_t W, H;
-  uint32_t cx, cy;  // 0x4B000000 + tile origin (x0, y0): pixel_fast yields tile coordinates
+  uint32_t cx, cy;  // 0x4B000000 + tile origin (x0, y0), in VGPRs: pixel_fast yields tile coordinates
   uint32_t tw, th;  // tile rectangle size (tiled batches)
   uint32_t tw8;     // tile row pitch in bytes
   uint64_t* vb;
@@ -158,8 +158,8 @@ __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const
   const uint32_t Hw[4] = {w.h.x, w.h.y, w.h.z, w.h.w};
   if constexpr (TILED) {
     // Tile coordinates straight from the pixel computation.  The classify
-    // kernel tiles a batch only when it has proved that every point's pixel
-    // lies inside the tile rectangle.
+    // kernel tiles a batch only when it has proved that the pixel of every
+    // point of the batch box lies inside the tile rectangle.
     // Early depth in LDS: the tile entry is read first and the 64-bit LDS
     // atomic is issued only by a key that beats it (a stale read only costs
     // an extra atomic: entries never increase).  Most points of a densely
@@ -183,9 +183,17 @@ __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      old[j] = 0;
-      if (ok[j])
-        old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if constexpr (CLS == CLS_INSIDE) {
+        // Every point of an INSIDE batch box (padding lanes decode to points
+        // of the box too) maps into the tile: the read needs no guard.
+        old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        old[j] = 0;
+        if (ok[j])
+          old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -263,6 +271,10 @@ __device__ void raster_points(const Loop& L, const RenderArgs& a, uint64_t* tile
     for (int d = 0; d < PREFETCH; ++d) {
       gi[d] = wave + d * WAVES;
       R[d] = load_group<K>(a, first, min(gi[d], glast), lane);
+      // keep the initial loads in the order of their use, the order the
+      // loop reissues them in: the loop's waits then count PREFETCH - 1
+      // younger loads on every path
+      __builtin_amdgcn_sched_barrier(0);
     }
     for (uint32_t j = 0; j < nj; j += PREFETCH) {
 #pragma unroll
@@ -298,6 +310,14 @@ __device__ void raster_points(const Loop& L, const RenderArgs& a, uint64_t* tile
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// A uniform value as a VGPR operand (the pixel subtraction takes its carry
+// from an SGPR and may read only one scalar operand).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+  uint32_t v;
+  asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+  return v;
+}
+
 // ---------------------------------------------------------------- classify
 // The per-batch prologue (Sec. 3.2 culling, Sec. 3.3 precision choice) for one
 // batch per thread, in binary64 without contraction:
@@ -310,7 +330,117 @@ __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_re
 //           has w <= 0); 10 bits if E < t10, 20 if E < t20, else 30;
 //  fold     P[r][j] = fp32(Pm[r][j] (size_j 2^-k)),
 //           t[r] = fp32(((Pm[r][0] min_x + Pm[r][1] min_y) + Pm[r][2] min_z) + Pm[r][3]).
-// Live batches are appended to a compact list (wave ballot + one atomic per wave).
+// decide_batch applies it to one batch and one view: returns whether the
+// batch is live; out receives its render record, li its level index.
+__device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (&Pm)[3][4], uint32_t W, uint32_t Hh,
+                                             int32_t precision, int32_t cull, float t10, float t20, LiveBatch& out,
+                                             bool& culled, int& li) {
+  bool live = false;
+  double H[3][8], M[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double amax = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double cx = (double)((c & 1) ? rec.mx[0] : rec.mn[0]);
+      const double cy = (double)((c & 2) ? rec.mx[1] : rec.mn[1]);
+      const double cz = (double)((c & 4) ? rec.mx[2] : rec.mn[2]);
+      H[r][c] = ((Pm[r][0] * cx + Pm[r][1] * cy) + Pm[r][2] * cz) + Pm[r][3];
+      const double ar = ((fabs(Pm[r][0] * cx) + fabs(Pm[r][1] * cy)) + fabs(Pm[r][2] * cz)) + fabs(Pm[r][3]);
+      if (ar > amax) amax = ar;
+    }
+    M[r] = 0x1p-16 * amax;
+  }
+  const double Wd = (double)W, Hd = (double)Hh;
+  bool behind = true, left = true, right = true, bottom = true, top = true, front = true;
+  bool safe = true, ins = true;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    behind = behind && (H[2][c] < -M[2]);
+    left = left && (H[0][c] < -M[0]);
+    right = right && (H[0][c] - Wd * H[2][c] > M[0] + Wd * M[2]);
+    bottom = bottom && (H[1][c] < -M[1]);
+    top = top && (H[1][c] - Hd * H[2][c] > M[1] + Hd * M[2]);
+    front = front && (H[2][c] > 0.0);
+    const bool sc = (H[2][c] - M[2] >= 0x1p-60) && (H[2][c] + M[2] <= 0x1p60);
+    safe = safe && sc;
+    ins = ins && sc && (H[0][c] > M[0]) && (H[0][c] - Wd * H[2][c] < -(M[0] + Wd * M[2])) && (H[1][c] > M[1]) &&
+          (H[1][c] - Hd * H[2][c] < -(M[1] + Hd * M[2]));
+  }
+  culled = cull && (behind || left || right || bottom || top);
+  if (!culled) {
+    double umin = __builtin_inf(), umax = -__builtin_inf(), vmin = __builtin_inf(), vmax = -__builtin_inf();
+    if (front) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double u = H[0][c] / H[2][c], v = H[1][c] / H[2][c];
+        if (u < umin) umin = u;
+        if (u > umax) umax = u;
+        if (v < vmin) vmin = v;
+        if (v > vmax) vmax = v;
+      }
+    }
+    int k;
+    if (precision == 10 || precision == 20 || precision == 30) {
+      k = precision;
+    } else {
+      double E = __builtin_inf();
+      if (front) {
+        const double ex = umax - umin, ey = vmax - vmin;
+        E = ex > ey ? ex : ey;
+      }
+      k = E < (double)t10 ? 10 : (E < (double)t20 ? 20 : 30);
+    }
+    const int cls = ins ? CLS_INSIDE : (safe ? CLS_PARTIAL : CLS_SLOW);
+    // Tile rectangle: the projected corners' box, one pixel wider on each
+    // side, clipped to the image (front batches only).  Every point's pixel
+    // lies inside it when the binary32 evaluation (hx, hw off by at most
+    // M/16 each) moves its quotient by less than half a pixel:
+    //   (Mx + max|u| Mw) / 16 / (min_c hw - Mw) < 1/2, and likewise for y.
+    uint32_t tiled = 0, x0 = 0, y0 = 0, tw = 0, th = 0;
+    double hwmin = H[2][0];
+#pragma unroll
+    for (int c = 1; c < 8; ++c) hwmin = fmin(hwmin, H[2][c]);
+    const double hwlo = hwmin - M[2];
+    const bool tight = front && hwlo > 0.0 &&
+                       M[0] + fmax(fabs(umin), fabs(umax)) * M[2] < 8.0 * hwlo &&
+                       M[1] + fmax(fabs(vmin), fabs(vmax)) * M[2] < 8.0 * hwlo;
+    if (tight && cls != CLS_SLOW) {
+      const double fx0 = fmax(floor(fmax(umin, -4.0)) - 1.0, 0.0);
+      const double fx1 = fmin(floor(fmin(umax, Wd + 4.0)) + 1.0, Wd - 1.0);
+      const double fy0 = fmax(floor(fmax(vmin, -4.0)) - 1.0, 0.0);
+      const double fy1 = fmin(floor(fmin(vmax, Hd + 4.0)) + 1.0, Hd - 1.0);
+      if (fx1 >= fx0 && fy1 >= fy0 && (fx1 - fx0 + 1.0) * (fy1 - fy0 + 1.0) <= (double)TILE_MAX) {
+        tiled = 1;
+        x0 = (uint32_t)fx0;
+        y0 = (uint32_t)fy0;
+        tw = (uint32_t)(fx1 - fx0) + 1u;
+        th = (uint32_t)(fy1 - fy0) + 1u;
+      }
+    }
+    const double scale = k == 10 ? 0x1p-10 : (k == 20 ? 0x1p-20 : 0x1p-30);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) out.P[r][j] = (float)(Pm[r][j] * (((double)rec.mx[j] - (double)rec.mn[j]) * scale));
+      out.t[r] = (float)(((Pm[r][0] * (double)rec.mn[0] + Pm[r][1] * (double)rec.mn[1]) +
+                          Pm[r][2] * (double)rec.mn[2]) +
+                         Pm[r][3]);
+    }
+    out.first = rec.first;
+    out.count = rec.count;
+    out.mode = (uint32_t)k | ((uint32_t)cls << 8) | (tiled << 16);
+    out.rect_xy = x0 | (y0 << 16);
+    out.rect_wh = tw | (th << 16);
+    out.pad[0] = out.pad[1] = out.pad[2] = 0;
+    live = true;
+    li = k / 10 - 1;
+  }
+  return live;
+}
+
+// One batch per thread; live batches are appended to a compact list (wave
+// ballot + one atomic per wave).
 template <bool CNT>
 __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
   const uint32_t b = blockIdx.x * 256u + threadIdx.x;
@@ -324,107 +454,7 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
   if (valid) {
     const BatchRec rec = a.batches[b];
     count = rec.count;
-    const double(&Pm)[3][4] = a.Pm;
-    double H[3][8], M[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      double amax = 0.0;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const double cx = (double)((c & 1) ? rec.mx[0] : rec.mn[0]);
-        const double cy = (double)((c & 2) ? rec.mx[1] : rec.mn[1]);
-        const double cz = (double)((c & 4) ? rec.mx[2] : rec.mn[2]);
-        H[r][c] = ((Pm[r][0] * cx + Pm[r][1] * cy) + Pm[r][2] * cz) + Pm[r][3];
-        const double ar = ((fabs(Pm[r][0] * cx) + fabs(Pm[r][1] * cy)) + fabs(Pm[r][2] * cz)) + fabs(Pm[r][3]);
-        if (ar > amax) amax = ar;
-      }
-      M[r] = 0x1p-16 * amax;
-    }
-    const double Wd = (double)a.W, Hd = (double)a.H;
-    bool behind = true, left = true, right = true, bottom = true, top = true, front = true;
-    bool safe = true, ins = true;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      behind = behind && (H[2][c] < -M[2]);
-      left = left && (H[0][c] < -M[0]);
-      right = right && (H[0][c] - Wd * H[2][c] > M[0] + Wd * M[2]);
-      bottom = bottom && (H[1][c] < -M[1]);
-      top = top && (H[1][c] - Hd * H[2][c] > M[1] + Hd * M[2]);
-      front = front && (H[2][c] > 0.0);
-      const bool sc = (H[2][c] - M[2] >= 0x1p-60) && (H[2][c] + M[2] <= 0x1p60);
-      safe = safe && sc;
-      ins = ins && sc && (H[0][c] > M[0]) && (H[0][c] - Wd * H[2][c] < -(M[0] + Wd * M[2])) && (H[1][c] > M[1]) &&
-            (H[1][c] - Hd * H[2][c] < -(M[1] + Hd * M[2]));
-    }
-    culled = a.cull && (behind || left || right || bottom || top);
-    if (!culled) {
-      double umin = __builtin_inf(), umax = -__builtin_inf(), vmin = __builtin_inf(), vmax = -__builtin_inf();
-      if (front) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const double u = H[0][c] / H[2][c], v = H[1][c] / H[2][c];
-          if (u < umin) umin = u;
-          if (u > umax) umax = u;
-          if (v < vmin) vmin = v;
-          if (v > vmax) vmax = v;
-        }
-      }
-      int k;
-      if (a.precision == 10 || a.precision == 20 || a.precision == 30) {
-        k = a.precision;
-      } else {
-        double E = __builtin_inf();
-        if (front) {
-          const double ex = umax - umin, ey = vmax - vmin;
-          E = ex > ey ? ex : ey;
-        }
-        k = E < (double)a.t10 ? 10 : (E < (double)a.t20 ? 20 : 30);
-      }
-      const int cls = ins ? CLS_INSIDE : (safe ? CLS_PARTIAL : CLS_SLOW);
-      // Tile rectangle: the projected corners' box, one pixel wider on each
-      // side, clipped to the image (front batches only).  Every point's pixel
-      // lies inside it when the binary32 evaluation (hx, hw off by at most
-      // M/16 each) moves its quotient by less than half a pixel:
-      //   (Mx + max|u| Mw) / 16 / (min_c hw - Mw) < 1/2, and likewise for y.
-      uint32_t tiled = 0, x0 = 0, y0 = 0, tw = 0, th = 0;
-      double hwmin = H[2][0];
-#pragma unroll
-      for (int c = 1; c < 8; ++c) hwmin = fmin(hwmin, H[2][c]);
-      const double hwlo = hwmin - M[2];
-      const bool tight = front && hwlo > 0.0 &&
-                         M[0] + fmax(fabs(umin), fabs(umax)) * M[2] < 8.0 * hwlo &&
-                         M[1] + fmax(fabs(vmin), fabs(vmax)) * M[2] < 8.0 * hwlo;
-      if (tight && cls != CLS_SLOW) {
-        const double fx0 = fmax(floor(fmax(umin, -4.0)) - 1.0, 0.0);
-        const double fx1 = fmin(floor(fmin(umax, Wd + 4.0)) + 1.0, Wd - 1.0);
-        const double fy0 = fmax(floor(fmax(vmin, -4.0)) - 1.0, 0.0);
-        const double fy1 = fmin(floor(fmin(vmax, Hd + 4.0)) + 1.0, Hd - 1.0);
-        if (fx1 >= fx0 && fy1 >= fy0 && (fx1 - fx0 + 1.0) * (fy1 - fy0 + 1.0) <= (double)TILE_MAX) {
-          tiled = 1;
-          x0 = (uint32_t)fx0;
-          y0 = (uint32_t)fy0;
-          tw = (uint32_t)(fx1 - fx0) + 1u;
-          th = (uint32_t)(fy1 - fy0) + 1u;
-        }
-      }
-      const double scale = k == 10 ? 0x1p-10 : (k == 20 ? 0x1p-20 : 0x1p-30);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) out.P[r][j] = (float)(Pm[r][j] * (((double)rec.mx[j] - (double)rec.mn[j]) * scale));
-        out.t[r] = (float)(((Pm[r][0] * (double)rec.mn[0] + Pm[r][1] * (double)rec.mn[1]) +
-                            Pm[r][2] * (double)rec.mn[2]) +
-                           Pm[r][3]);
-      }
-      out.first = rec.first;
-      out.count = rec.count;
-      out.mode = (uint32_t)k | ((uint32_t)cls << 8) | (tiled << 16);
-      out.rect_xy = x0 | (y0 << 16);
-      out.rect_wh = tw | (th << 16);
-      out.pad[0] = out.pad[1] = out.pad[2] = 0;
-      live = true;
-      li = k / 10 - 1;
-    }
+    live = decide_batch(rec, a.Pm, a.W, a.H, a.precision, a.cull, a.t10, a.t20, out, culled, li);
   }
   if constexpr (CNT) {
     const uint64_t mv = __ballot(valid), mc = __ballot(valid && culled);
@@ -481,7 +511,7 @@ template <bool CNT>
 __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
   __shared__ uint64_t tile[TILE_MAX];
   __shared__ uint32_t s_next;
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
   const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
   for (uint32_t e = tid; e < TILE_MAX / 2; e += THREADS) reinterpret_cast<uint4*>(tile)[e] = ones;
   // this workgroup's queue: workgroups are spread over the queues round-robin
@@ -516,8 +546,8 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
     const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
     const bool tiled = (mode >> 16) & 1u;
     // opaque to the optimiser, so that each biased constant stays one operand
-    L.cx = uni(0x4B000000u + (tiled ? x0 : 0u));
-    L.cy = uni(0x4B000000u + (tiled ? y0 : 0u));
+    L.cx = in_vgpr(uni(0x4B000000u + (tiled ? x0 : 0u)));
+    L.cy = in_vgpr(uni(0x4B000000u + (tiled ? y0 : 0u)));
     if (tiled) {
       if (k == 10) raster_by_class<10, true>(cls, L, a, tile, first, count, wave, lane, natom);
       else if (k == 20) raster_by_class<20, true>(cls, L, a, tile, first, count, wave, lane, natom);
