@@ -141,6 +141,36 @@ pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, ui
  * coordinate is NaN or Inf. */
 pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton);
 
+/* One view of a multi-view render: matrices and image size as for
+ * pr_render, and the view's visibility buffer (uint64[h*w], device, 16-byte
+ * aligned). */
+#define PR_MAX_VIEWS 64
+typedef struct {
+  float view[16], proj[16];
+  uint32_t w, h;
+  uint64_t* visbuf;
+} pr_view;
+
+/* Bytes of device workspace pr_render_views needs for this (built) cloud and
+ * nviews views (1 <= nviews <= PR_MAX_VIEWS). */
+pr_status pr_views_work_bytes(const pr_cloud* cloud, uint32_t nviews, uint64_t* out);
+
+/* Render nviews views (stereo pairs, camera arrays) of one cloud with one
+ * persistent render launch (Sec. 3.7: both eyes of a VR frame in one pass).
+ * The per-batch prologue (culling, precision level, tile) runs for every
+ * (batch, view) pair exactly as in pr_render; each workgroup then renders a
+ * batch for all of its live views in turn, so the batch's coordinate words
+ * are streamed from HBM once per frame instead of once per view.  Every
+ * view's visibility buffer equals pr_render of that view with the same opts,
+ * bit for bit.  opts apply to every view (accumulate: no view is cleared;
+ * counters: pr_stats sums over all (batch, view) pairs).  work: caller-owned
+ * device memory of at least pr_views_work_bytes bytes, 256-byte aligned; it
+ * must not be used by another call in flight.  Asynchronous.  PR_ERANGE for
+ * nviews or image sizes outside the limits, PR_ENONFINITE for non-finite
+ * matrices, PR_ESTATE before pr_build_batches. */
+pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                          const pr_render_opts* opts, void* work, uint64_t work_bytes);
+
 /* Fill visbuf (uint64[h*w], device, 16-byte aligned) with PR_EMPTY (the
  * frame clear of Sec. 4.3).  Asynchronous. */
 pr_status pr_clear(pr_ctx* ctx, uint64_t* visbuf, uint32_t w, uint32_t h);

@@ -18,11 +18,13 @@ lib = ctypes.CDLL(LIB_PATH)
 
 PR_ADAPTIVE, PR_FORCE10, PR_FORCE20, PR_FORCE30 = 0, 10, 20, 30
 PR_EMPTY = 0xFFFFFFFFFFFFFFFF
+PR_MAX_VIEWS = 64
 _STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "PR_ESTATE",
            -5: "PR_ENONFINITE", -6: "PR_ERANGE"}
 
 EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_load_points", "pr_build_batches",
-            "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free"]
+            "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
+            "pr_views_work_bytes", "pr_render_views"]
 
 
 class PrError(RuntimeError):
@@ -52,6 +54,11 @@ class RenderOpts(ctypes.Structure):
         return cls(precision, cull, t10, t20, counters, accumulate)
 
 
+class View(ctypes.Structure):
+    _fields_ = [("view", ctypes.c_float * 16), ("proj", ctypes.c_float * 16), ("w", ctypes.c_uint32),
+                ("h", ctypes.c_uint32), ("visbuf", ctypes.c_void_p)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("culled", ctypes.c_uint64), ("points", ctypes.c_uint64),
                 ("level_batches", ctypes.c_uint64 * 3), ("level_points", ctypes.c_uint64 * 3),
@@ -76,12 +83,14 @@ lib.pr_clear.argtypes = [_P, _P, _U32, _U32]
 lib.pr_render.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts), _P]
 lib.pr_resolve.argtypes = [_P, _P, _P, _U32, _U32, _U32, _P]
 lib.pr_get_stats.argtypes = [_P, ctypes.POINTER(Stats)]
+lib.pr_views_work_bytes.argtypes = [_P, _U32, ctypes.POINTER(_U64)]
+lib.pr_render_views.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64]
 lib.pr_sync.argtypes = [_P]
 lib.pr_cloud_info.argtypes = [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U32)]
 lib.pr_cloud_free.argtypes = [_P]
 lib.pr_cloud_free.restype = None
 for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
-           "pr_get_stats", "pr_sync", "pr_cloud_info"):
+           "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -151,6 +160,23 @@ def pr_render(ctx, cloud, view, proj, w: int, h: int, opts: RenderOpts | None, v
     p, pp = _mat16(proj)
     _check(lib.pr_render(ctx, cloud, vp, pp, w, h, ctypes.byref(opts) if opts is not None else None, _ptr(visbuf)),
            "pr_render")
+
+
+def pr_views_work_bytes(cloud, nviews: int) -> int:
+    out = _U64()
+    _check(lib.pr_views_work_bytes(cloud, nviews, ctypes.byref(out)), "pr_views_work_bytes")
+    return out.value
+
+
+def pr_render_views(ctx, cloud, views, opts: RenderOpts | None, work, work_bytes: int):
+    """views: sequence of (view, proj, w, h, visbuf); work: device buffer of pr_views_work_bytes bytes."""
+    arr = (View * len(views))()
+    for i, (v, p, w, h, vb) in enumerate(views):
+        arr[i].view[:] = [float(x) for x in np.asarray(v, dtype=np.float32).reshape(16)]
+        arr[i].proj[:] = [float(x) for x in np.asarray(p, dtype=np.float32).reshape(16)]
+        arr[i].w, arr[i].h, arr[i].visbuf = w, h, _ptr(vb)
+    _check(lib.pr_render_views(ctx, cloud, arr, len(views), ctypes.byref(opts) if opts is not None else None,
+                               _ptr(work), work_bytes), "pr_render_views")
 
 
 def pr_resolve(ctx, cloud, visbuf, w: int, h: int, clear_rgba: int, rgba_out):

@@ -38,7 +38,7 @@ static_assert(sizeof(LiveBatch) == 80, "live batch record is 80 bytes");
 // 128-byte line: one shared counter serialises every workgroup's request.
 constexpr uint32_t RENDER_QUEUES = 8;
 struct FrameHeader {
-  uint32_t live_count;  // live batches written by classify
+  uint32_t live_count;  // live batches (single view) or runs (several views) written by classify
   uint32_t pad[31];
   uint32_t queue[RENDER_QUEUES][32];  // queue[q][0]: next position of queue q
 };
@@ -62,11 +62,69 @@ struct RenderArgs {
   uint32_t grid;    // persistent render workgroups
 };
 
+// ---- several views in one launch
+// A live batch of a multi-view frame: the batch and the mask of its live
+// views among views view0 .. view0 + 63.  Its render records sit at
+// sub[batch * nviews + view].
+constexpr uint32_t MAX_VIEWS = 64;
+constexpr uint32_t VIEW_CHUNK = 16;  // views per classify launch (kernel-argument size)
+struct Run {
+  uint32_t batch, view0;
+  uint64_t mask;
+};
+static_assert(sizeof(Run) == 16, "run record is 16 bytes");
+struct ViewIn {  // what the prologue needs of one view
+  double Pm[3][4];
+  uint32_t W, H;
+};
+struct ViewOut {  // what the point loop needs of one view
+  uint64_t* vb;
+  uint32_t W, H;
+};
+struct ClassifyViewsArgs {
+  const BatchRec* batches;
+  LiveBatch* sub;
+  Run* runs;
+  FrameHeader* hdr;
+  uint64_t* stats;
+  uint32_t nb, nviews, view0, nchunk;  // all views, first view of this launch, views in it
+  int32_t precision, cull;
+  float t10, t20;
+  ViewIn v[VIEW_CHUNK];
+};
+struct RenderViewsArgs {
+  const uint32_t* low;
+  const uint32_t* med;
+  const uint32_t* high;
+  const LiveBatch* sub;
+  const Run* runs;
+  FrameHeader* hdr;
+  uint64_t* stats;
+  uint32_t nviews, grid;
+  ViewOut v[MAX_VIEWS];
+};
+struct ClearViewsArgs {
+  FrameHeader* hdr;
+  uint64_t* stats;
+  uint32_t nviews, clear, reset_stats;
+  ViewOut v[MAX_VIEWS];
+};
+// header, runs (one per batch and launch of classify), records (one per batch and view)
+inline uint64_t views_work_bytes(uint64_t nb, uint32_t nviews) {
+  const uint64_t chunks = (nviews + VIEW_CHUNK - 1) / VIEW_CHUNK;
+  return sizeof(FrameHeader) + sizeof(Run) * nb * chunks + sizeof(LiveBatch) * nb * nviews;
+}
+
 // ---- render path (kern_render.hip)
 hipError_t launch_clear(uint64_t* vb, uint64_t npix, DevBlock* dev, FrameHeader* hdr, int reset_stats, hipStream_t s);
 // classify (cull, level, fold, compaction) followed by the persistent render kernel
 hipError_t launch_render(const RenderArgs& a, hipStream_t s);
 uint32_t render_grid(int device);
+// several views: clear, classify per chunk of VIEW_CHUNK views, one persistent render launch
+hipError_t launch_clear_views(const ClearViewsArgs& a, hipStream_t s);
+hipError_t launch_classify_views(const ClassifyViewsArgs& a, int counters, hipStream_t s);
+hipError_t launch_render_views(const RenderViewsArgs& a, uint64_t max_runs, int counters, hipStream_t s);
+uint32_t render_views_grid(int device);
 hipError_t launch_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint64_t ncolors,
                           uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
 

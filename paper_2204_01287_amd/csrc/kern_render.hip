@@ -237,8 +237,15 @@ __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const
   }
 }
 
+// The coordinate streams of the cloud (low, medium, high words).
+struct Streams {
+  const uint32_t* low;
+  const uint32_t* med;
+  const uint32_t* high;
+};
+
 template <int K>
-__device__ __forceinline__ Words load_group(const RenderArgs& a, uint32_t first, uint32_t g, uint32_t lane) {
+__device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, uint32_t g, uint32_t lane) {
   const uint32_t q = first / 4 + g * 64 + lane;  // first is a multiple of 4
   Words w;
   w.l = reinterpret_cast<const uint4*>(a.low)[q];
@@ -253,7 +260,7 @@ __device__ __forceinline__ Words load_group(const RenderArgs& a, uint32_t first,
 // groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
 // 16-byte load per word).  Wave 0 also takes the ragged tail.
 template <int K, int CLS, bool TILED>
-__device__ void raster_points(const Loop& L, const RenderArgs& a, uint64_t* tile, uint32_t first, uint32_t count,
+__device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
                               uint32_t wave, uint32_t lane, uint32_t& natom) {
   const uint32_t ngrp = count >> 8;
   const uint32_t nj = wave < ngrp ? (ngrp - wave + WAVES - 1) / WAVES : 0;  // this wave's groups
@@ -490,9 +497,93 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
   }
 }
 
+// Several views: one thread per batch runs the prologue for each view of
+// this launch; the records go to fixed slots (batch, view), the batch's live
+// views to one run record (wave ballot + one atomic per wave).
+template <bool CNT>
+__global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
+  const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
+  const bool valid = b < a.nb;
+  uint64_t mask = 0;
+  uint64_t nculled = 0, pts = 0, lp[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+  if (valid) {
+    const BatchRec rec = a.batches[b];
+    for (uint32_t v = 0; v < a.nchunk; ++v) {
+      LiveBatch out;
+      bool culled = false;
+      int li = 0;
+      if (decide_batch(rec, a.v[v].Pm, a.v[v].W, a.v[v].H, a.precision, a.cull, a.t10, a.t20, out, culled, li)) {
+        a.sub[(uint64_t)b * a.nviews + a.view0 + v] = out;
+        mask |= 1ull << v;
+        if constexpr (CNT) {
+          pts += rec.count;
+          lp[li] += rec.count;
+          lb[li] += 1;
+        }
+      }
+      if constexpr (CNT) nculled += culled ? 1u : 0u;
+    }
+  }
+  if constexpr (CNT) {
+    uint64_t nbv = valid ? a.nchunk : 0u;
+    for (int o = 32; o > 0; o >>= 1) {
+      nbv += __shfl_xor(nbv, o);
+      nculled += __shfl_xor(nculled, o);
+      pts += __shfl_xor(pts, o);
+      for (int q = 0; q < 3; ++q) {
+        lp[q] += __shfl_xor(lp[q], o);
+        lb[q] += __shfl_xor(lb[q], o);
+      }
+    }
+    if (lane == 0 && nbv) {
+      atomicAdd((unsigned long long*)&a.stats[ST_BATCHES], (unsigned long long)nbv);
+      if (nculled) atomicAdd((unsigned long long*)&a.stats[ST_CULLED], (unsigned long long)nculled);
+      if (pts) atomicAdd((unsigned long long*)&a.stats[ST_POINTS], (unsigned long long)pts);
+      for (int q = 0; q < 3; ++q) {
+        if (lb[q]) atomicAdd((unsigned long long*)&a.stats[ST_LB0 + q], (unsigned long long)lb[q]);
+        if (lp[q]) atomicAdd((unsigned long long*)&a.stats[ST_LP0 + q], (unsigned long long)lp[q]);
+      }
+    }
+  }
+  const bool live = mask != 0;
+  const uint64_t m = __ballot(live);
+  uint32_t base = 0;
+  if (lane == 0 && m) base = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(m));
+  base = __shfl(base, 0);
+  if (live) {
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    Run r;
+    r.batch = b;
+    r.view0 = a.view0;
+    r.mask = mask;
+    a.runs[base + (uint32_t)__popcll(m & lt)] = r;
+  }
+}
+
+// Clears every view's visibility buffer (blockIdx.y = view) unless
+// accumulating, and resets the frame's work queue and counters.
+__global__ void __launch_bounds__(256) k_clear_views(ClearViewsArgs a) {
+  const ViewOut& v = a.v[blockIdx.y];
+  if (a.clear) {
+    const uint64_t npix = (uint64_t)v.W * v.H, n4 = npix / 2;
+    uint4* const vb4 = reinterpret_cast<uint4*>(v.vb);
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint64_t i = tid; i < n4; i += stride) vb4[i] = ones;
+    if (tid == 0 && (npix & 1)) v.vb[npix - 1] = ~0ull;
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (threadIdx.x == 0) a.hdr->live_count = 0;
+    if (threadIdx.x < RENDER_QUEUES) a.hdr->queue[threadIdx.x][0] = 0;
+    if (a.reset_stats && threadIdx.x < 16) a.stats[threadIdx.x] = 0;
+  }
+}
+
 // ------------------------------------------------------------------ render
 template <int K, bool TILED>
-__device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const RenderArgs& a, uint64_t* tile,
+__device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const Streams& a, uint64_t* tile,
                                                 uint32_t first, uint32_t count, uint32_t wave, uint32_t lane,
                                                 uint32_t& natom) {
   if (cls == CLS_INSIDE)
@@ -503,22 +594,94 @@ __device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const Re
     raster_points<K, CLS_SLOW, false>(L, a, tile, first, count, wave, lane, natom);
 }
 
+// One live batch of one view by the whole workgroup: its points into the LDS
+// tile (or straight into the global buffer), then the tile flush.  The LDS
+// tile is all PR_EMPTY between batches (the flush resets what it reads), so a
+// batch needs two barriers: one after its points, one after its flush.
+// publish: thread 0 stores next into s_next between the barriers (the
+// workgroup reads it after the second one).
+__device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, uint32_t H, uint64_t* vb,
+                                             const Streams& st, uint64_t* tile, uint32_t tid, uint32_t wave,
+                                             uint32_t lane, bool publish, uint32_t next, uint32_t* s_next,
+                                             uint32_t& natom) {
+  Loop L;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) L.P[r][j] = rec.P[r][j];
+    L.t[r] = rec.t[r];
+  }
+  L.W = W;
+  L.H = H;
+  L.vb = vb;
+  const uint32_t mode = rec.mode, rxy = rec.rect_xy, rwh = rec.rect_wh;
+  const uint32_t first = rec.first, count = rec.count;
+  const uint32_t x0 = rxy & 0xFFFFu, y0 = rxy >> 16;
+  L.tw = rwh & 0xFFFFu;
+  L.th = rwh >> 16;
+  L.tw8 = L.tw * 8u;
+  const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
+  const bool tiled = (mode >> 16) & 1u;
+  L.cx = in_vgpr(uni(0x4B000000u + (tiled ? x0 : 0u)));
+  L.cy = in_vgpr(uni(0x4B000000u + (tiled ? y0 : 0u)));
+  if (tiled) {
+    if (k == 10) raster_by_class<10, true>(cls, L, st, tile, first, count, wave, lane, natom);
+    else if (k == 20) raster_by_class<20, true>(cls, L, st, tile, first, count, wave, lane, natom);
+    else raster_by_class<30, true>(cls, L, st, tile, first, count, wave, lane, natom);
+  } else {
+    if (k == 10) raster_by_class<10, false>(cls, L, st, tile, first, count, wave, lane, natom);
+    else if (k == 20) raster_by_class<20, false>(cls, L, st, tile, first, count, wave, lane, natom);
+    else raster_by_class<30, false>(cls, L, st, tile, first, count, wave, lane, natom);
+  }
+  __syncthreads();  // the batch's points are all in the tile; s_next has been read
+  if (publish && tid == 0) *s_next = next;
+  if (tiled) {
+    // Flush: every covered tile pixel once into the global buffer, leaving
+    // the entry PR_EMPTY for the next batch.  Most covered pixels improve
+    // the global minimum, so the atomic is issued without a prior read
+    // (no round trip on this path).
+    const uint32_t n = L.tw * L.th;
+    for (uint32_t e = tid; e < n; e += THREADS) {
+      const uint64_t v = tile[e];
+      if (v != ~0ull) {
+        tile[e] = ~0ull;
+        const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
+        __hip_atomic_fetch_min(L.vb + ((y0 + ly) * L.W + (x0 + lx)), v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        natom++;
+      }
+    }
+  }
+  __syncthreads();  // tile clean again; s_next visible
+}
+
+__device__ __forceinline__ void fill_tile(uint64_t* tile, uint32_t tid) {
+  const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+  for (uint32_t e = tid; e < TILE_MAX / 2; e += THREADS) reinterpret_cast<uint4*>(tile)[e] = ones;
+}
+
+template <bool CNT>
+__device__ __forceinline__ void add_atomics(uint64_t* stats, uint32_t natom, uint32_t lane) {
+  if constexpr (CNT) {
+    for (int o = 32; o > 0; o >>= 1) natom += __shfl_xor(natom, o);
+    if (lane == 0 && natom) atomicAdd((unsigned long long*)&stats[ST_ATOMICS], (unsigned long long)natom);
+  }
+}
+
 // Persistent: each workgroup takes live batches from its work queue until it
-// is empty.  The LDS tile is all PR_EMPTY between batches (the flush resets
-// what it reads), so a batch needs two barriers: one after its points, one
-// after its flush.
+// is empty.  The next batch is requested while the current one renders.
 template <bool CNT>
 __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
   __shared__ uint64_t tile[TILE_MAX];
   __shared__ uint32_t s_next;
   const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
-  const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
-  for (uint32_t e = tid; e < TILE_MAX / 2; e += THREADS) reinterpret_cast<uint4*>(tile)[e] = ones;
+  fill_tile(tile, tid);
   // this workgroup's queue: workgroups are spread over the queues round-robin
   const uint32_t q = blockIdx.x % RENDER_QUEUES;
   uint32_t* const qc = &a.hdr->queue[q][0];
   if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
   const uint32_t nlive = a.hdr->live_count;
+  const Streams st = {a.low, a.med, a.high};
   __syncthreads();
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
@@ -526,63 +689,46 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
     // Take the next batch now; the atomic's latency hides behind this batch.
     uint32_t grab = 0;
     if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
-    const LiveBatch& rec = a.live[i];
-    Loop L;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-#pragma unroll
-      for (int j = 0; j < 3; ++j) L.P[r][j] = rec.P[r][j];
-      L.t[r] = rec.t[r];
-    }
-    L.W = a.W;
-    L.H = a.H;
-    L.vb = a.vb;
-    const uint32_t mode = rec.mode, rxy = rec.rect_xy, rwh = rec.rect_wh;
-    const uint32_t first = rec.first, count = rec.count;
-    const uint32_t x0 = rxy & 0xFFFFu, y0 = rxy >> 16;
-    L.tw = rwh & 0xFFFFu;
-    L.th = rwh >> 16;
-    L.tw8 = L.tw * 8u;
-    const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
-    const bool tiled = (mode >> 16) & 1u;
-    // opaque to the optimiser, so that each biased constant stays one operand
-    L.cx = in_vgpr(uni(0x4B000000u + (tiled ? x0 : 0u)));
-    L.cy = in_vgpr(uni(0x4B000000u + (tiled ? y0 : 0u)));
-    if (tiled) {
-      if (k == 10) raster_by_class<10, true>(cls, L, a, tile, first, count, wave, lane, natom);
-      else if (k == 20) raster_by_class<20, true>(cls, L, a, tile, first, count, wave, lane, natom);
-      else raster_by_class<30, true>(cls, L, a, tile, first, count, wave, lane, natom);
-    } else {
-      if (k == 10) raster_by_class<10, false>(cls, L, a, tile, first, count, wave, lane, natom);
-      else if (k == 20) raster_by_class<20, false>(cls, L, a, tile, first, count, wave, lane, natom);
-      else raster_by_class<30, false>(cls, L, a, tile, first, count, wave, lane, natom);
-    }
-    __syncthreads();  // the batch's points are all in the tile; s_next has been read
-    if (tid == 0) s_next = grab;
-    if (tiled) {
-      // Flush: every covered tile pixel once into the global buffer, leaving
-      // the entry PR_EMPTY for the next batch.  Most covered pixels improve
-      // the global minimum, so the atomic is issued without a prior read
-      // (no round trip on this path).
-      const uint32_t n = L.tw * L.th;
-      for (uint32_t e = tid; e < n; e += THREADS) {
-        const uint64_t v = tile[e];
-        if (v != ~0ull) {
-          tile[e] = ~0ull;
-          const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
-          __hip_atomic_fetch_min(L.vb + ((y0 + ly) * L.W + (x0 + lx)), v, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-          natom++;
-        }
-      }
-    }
-    __syncthreads();  // tile clean again; s_next visible
+    render_batch(a.live[i], a.W, a.H, a.vb, st, tile, tid, wave, lane, true, grab, &s_next, natom);
     i = uni(s_next);
   }
-  if constexpr (CNT) {
-    for (int o = 32; o > 0; o >>= 1) natom += __shfl_xor(natom, o);
-    if (lane == 0 && natom) atomicAdd((unsigned long long*)&a.stats[ST_ATOMICS], (unsigned long long)natom);
+  add_atomics<CNT>(a.stats, natom, lane);
+}
+
+// Several views in one launch: the work items are runs (a batch and its live
+// views); the workgroup renders the batch once per view, so its coordinate
+// words come from HBM once and from the caches for the further views.
+template <bool CNT>
+__global__ void __launch_bounds__(THREADS) k_render_views(RenderViewsArgs a) {
+  __shared__ uint64_t tile[TILE_MAX];
+  __shared__ uint32_t s_next;
+  const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
+  fill_tile(tile, tid);
+  const uint32_t q = blockIdx.x % RENDER_QUEUES;
+  uint32_t* const qc = &a.hdr->queue[q][0];
+  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+  const uint32_t nruns = a.hdr->live_count;
+  const Streams st = {a.low, a.med, a.high};
+  __syncthreads();
+  uint32_t i = uni(s_next);
+  uint32_t natom = 0;
+  while (i < nruns) {
+    uint32_t grab = 0;
+    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    const Run run = a.runs[i];
+    uint64_t mask = run.mask;
+    bool publish = true;
+    while (mask) {
+      const uint32_t v = run.view0 + (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+      mask &= mask - 1;
+      const ViewOut& vo = a.v[v];
+      render_batch(a.sub[(uint64_t)run.batch * a.nviews + v], vo.W, vo.H, vo.vb, st, tile, tid, wave, lane, publish,
+                   grab, &s_next, natom);
+      publish = false;
+    }
+    i = uni(s_next);
   }
+  add_atomics<CNT>(a.stats, natom, lane);
 }
 
 // ------------------------------------------------------------------ resolve
@@ -644,6 +790,48 @@ hipError_t launch_render(const RenderArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_classify<false>, dim3(cblocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_render<false>, dim3(rblocks), dim3(THREADS), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+uint32_t render_views_grid(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_views<false>, THREADS, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  return (uint32_t)(per_cu * cus);
+}
+
+hipError_t launch_clear_views(const ClearViewsArgs& a, hipStream_t s) {
+  uint64_t maxpix = 0;
+  for (uint32_t v = 0; v < a.nviews; ++v) {
+    const uint64_t p = (uint64_t)a.v[v].W * a.v[v].H;
+    if (p > maxpix) maxpix = p;
+  }
+  uint64_t blocks = a.clear ? (maxpix / 2 + 255) / 256 : 1;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_clear_views, dim3((uint32_t)blocks, a.nviews), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify_views(const ClassifyViewsArgs& a, int counters, hipStream_t s) {
+  if (a.nb == 0) return hipSuccess;
+  const uint32_t blocks = (a.nb + 255) / 256;
+  if (counters)
+    hipLaunchKernelGGL(k_classify_views<true>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_classify_views<false>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_views(const RenderViewsArgs& a, uint64_t max_runs, int counters, hipStream_t s) {
+  if (max_runs == 0) return hipSuccess;
+  const uint32_t blocks = a.grid < max_runs ? a.grid : (uint32_t)max_runs;
+  if (counters)
+    hipLaunchKernelGGL(k_render_views<true>, dim3(blocks), dim3(THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_render_views<false>, dim3(blocks), dim3(THREADS), 0, s, a);
   return hipGetLastError();
 }
 

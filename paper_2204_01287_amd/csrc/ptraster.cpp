@@ -18,7 +18,8 @@ struct pr_ctx {
   int device;
   hipStream_t stream;
   ptr::DevBlock* dev;  // counters and flags (device memory)
-  uint32_t render_grid;  // persistent render workgroups that fit on the device at once
+  uint32_t render_grid;        // persistent render workgroups that fit on the device at once
+  uint32_t render_views_grid;  // the same for the multi-view render kernel
 };
 
 struct pr_cloud {
@@ -135,6 +136,7 @@ pr_status pr_create(int device, void* hip_stream, pr_ctx** out) {
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->dev = nullptr;
   c->render_grid = ptr::render_grid(device);
+  c->render_views_grid = ptr::render_views_grid(device);
   e = hipMalloc(reinterpret_cast<void**>(&c->dev), 4096);
   if (e != hipSuccess) {
     delete c;
@@ -298,6 +300,98 @@ pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], co
   a.t10 = o.t10;
   a.t20 = o.t20;
   HIP_TRY(ptr::launch_render(a, ctx->stream), "render");
+  return PR_OK;
+}
+
+pr_status pr_views_work_bytes(const pr_cloud* cloud, uint32_t nviews, uint64_t* out) {
+  if (!cloud || !out) return fail(PR_EINVAL, "pr_views_work_bytes: NULL argument");
+  if (nviews < 1 || nviews > PR_MAX_VIEWS) return fail(PR_ERANGE, "pr_views_work_bytes: nviews %u not in 1..%d", nviews, PR_MAX_VIEWS);
+  if (!cloud->built) return fail(PR_ESTATE, "pr_views_work_bytes: cloud is not built");
+  *out = a256(ptr::views_work_bytes(cloud->nb, nviews));
+  return PR_OK;
+}
+
+pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                          const pr_render_opts* opts, void* work, uint64_t work_bytes) {
+  if (!ctx || !cloud || !views || !work) return fail(PR_EINVAL, "pr_render_views: NULL argument");
+  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_render_views: cloud belongs to another context");
+  if (!cloud->built) return fail(PR_ESTATE, "pr_render_views: cloud is not built (call pr_build_batches)");
+  if (nviews < 1 || nviews > PR_MAX_VIEWS) return fail(PR_ERANGE, "pr_render_views: nviews %u not in 1..%d", nviews, PR_MAX_VIEWS);
+  if (reinterpret_cast<uintptr_t>(work) & 255u) return fail(PR_EINVAL, "pr_render_views: work must be 256-byte aligned");
+  if (work_bytes < ptr::views_work_bytes(cloud->nb, nviews))
+    return fail(PR_EINVAL, "pr_render_views: work holds %llu bytes, %llu needed", (unsigned long long)work_bytes,
+                (unsigned long long)ptr::views_work_bytes(cloud->nb, nviews));
+  pr_render_opts o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0};
+  if (opts) o = *opts;
+  if (o.precision != PR_ADAPTIVE && o.precision != PR_FORCE10 && o.precision != PR_FORCE20 &&
+      o.precision != PR_FORCE30)
+    return fail(PR_EINVAL, "pr_render_views: precision %d is not 0, 10, 20 or 30", o.precision);
+  if (std::isnan(o.t10) || std::isnan(o.t20)) return fail(PR_EINVAL, "pr_render_views: NaN threshold");
+  for (uint32_t v = 0; v < nviews; ++v) {
+    const pr_view& pv = views[v];
+    if (!pv.visbuf) return fail(PR_EINVAL, "pr_render_views: view %u has no visbuf", v);
+    if (pr_status s = check_dims(pv.w, pv.h)) return s;
+    if (reinterpret_cast<uintptr_t>(pv.visbuf) & 15u)
+      return fail(PR_EINVAL, "pr_render_views: visbuf of view %u must be 16-byte aligned", v);
+    for (int i = 0; i < 16; ++i)
+      if (!std::isfinite(pv.view[i]) || !std::isfinite(pv.proj[i]))
+        return fail(PR_ENONFINITE, "pr_render_views: non-finite matrix in view %u", v);
+  }
+  if (pr_status s = set_device(ctx)) return s;
+  const uint64_t nb = cloud->nb;
+  const uint32_t nchunks = (nviews + ptr::VIEW_CHUNK - 1) / ptr::VIEW_CHUNK;
+  ptr::FrameHeader* hdr = static_cast<ptr::FrameHeader*>(work);
+  ptr::Run* runs = reinterpret_cast<ptr::Run*>(hdr + 1);
+  ptr::LiveBatch* sub = reinterpret_cast<ptr::LiveBatch*>(runs + nb * nchunks);
+
+  ptr::ClearViewsArgs ca;
+  std::memset(&ca, 0, sizeof ca);
+  ca.hdr = hdr;
+  ca.stats = ctx->dev->stats;
+  ca.nviews = nviews;
+  ca.clear = o.accumulate ? 0u : 1u;
+  ca.reset_stats = o.counters ? 1u : 0u;
+  for (uint32_t v = 0; v < nviews; ++v) ca.v[v] = {views[v].visbuf, views[v].w, views[v].h};
+  HIP_TRY(ptr::launch_clear_views(ca, ctx->stream), "clear views");
+
+  for (uint32_t c = 0; c < nchunks; ++c) {
+    ptr::ClassifyViewsArgs k;
+    std::memset(&k, 0, sizeof k);
+    k.batches = static_cast<const ptr::BatchRec*>(cloud->bufs.batches);
+    k.sub = sub;
+    k.runs = runs;
+    k.hdr = hdr;
+    k.stats = ctx->dev->stats;
+    k.nb = (uint32_t)nb;
+    k.nviews = nviews;
+    k.view0 = c * ptr::VIEW_CHUNK;
+    k.nchunk = nviews - k.view0 < ptr::VIEW_CHUNK ? nviews - k.view0 : ptr::VIEW_CHUNK;
+    k.precision = o.precision;
+    k.cull = o.cull ? 1 : 0;
+    k.t10 = o.t10;
+    k.t20 = o.t20;
+    for (uint32_t v = 0; v < k.nchunk; ++v) {
+      const pr_view& pv = views[k.view0 + v];
+      frame_matrix(pv.view, pv.proj, pv.w, pv.h, k.v[v].Pm);
+      k.v[v].W = pv.w;
+      k.v[v].H = pv.h;
+    }
+    HIP_TRY(ptr::launch_classify_views(k, o.counters ? 1 : 0, ctx->stream), "classify views");
+  }
+
+  ptr::RenderViewsArgs r;
+  std::memset(&r, 0, sizeof r);
+  r.low = static_cast<const uint32_t*>(cloud->bufs.low);
+  r.med = static_cast<const uint32_t*>(cloud->bufs.med);
+  r.high = static_cast<const uint32_t*>(cloud->bufs.high);
+  r.sub = sub;
+  r.runs = runs;
+  r.hdr = hdr;
+  r.stats = ctx->dev->stats;
+  r.nviews = nviews;
+  r.grid = ctx->render_views_grid;
+  for (uint32_t v = 0; v < nviews; ++v) r.v[v] = {views[v].visbuf, views[v].w, views[v].h};
+  HIP_TRY(ptr::launch_render_views(r, nb * nchunks, o.counters ? 1 : 0, ctx->stream), "render views");
   return PR_OK;
 }
 

@@ -8,7 +8,8 @@ The oracle builds and renders the same cloud.  The whole build (positions in ren
 batch records, low/med/high words), every visibility buffer, every framebuffer and the frame counters are compared
 element by element.
 
-C3 -- 2,000,000,000-point terrain (index generation order, Morton build), stereo pair 2 x 2016 x 2240.  The oracle
+C3 -- 2,000,000,000-point terrain (index generation order, Morton build), stereo pair 2 x 2016 x 2240, one launch
+per eye and both eyes in one multi-view launch (pr_render_views).  The oracle
 cannot sort 2e9 points in test time, so the device's Morton permutation is checked by the two properties that make
 it unique:
   * it is a permutation of 0..n-1;
@@ -276,3 +277,26 @@ def test_c3_build_full(c3):
 def test_c3_stereo_eye(ctx, c3, eye):
     cam = c3.wl["cams"][eye]
     _check_eye(ctx, c3.cloud["handle"], c3.built, c3.colors, cam, c3.nb, f"C3 eye {eye}")
+
+
+def test_c3_stereo_one_launch(ctx, c3):
+    """Both eyes through pr_render_views (one persistent launch) equal the oracle's single-eye renders."""
+    import torch
+    import paper_2204_01287_amd as pr
+
+    cams = c3.wl["cams"]
+    vbs = [torch.empty(c.width * c.height, dtype=torch.int64, device="cuda") for c in cams]
+    need = pr.pr_views_work_bytes(c3.cloud["handle"], len(cams))
+    work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    say("C3: both eyes in one multi-view launch")
+    pr.pr_render_views(ctx.handle, c3.cloud["handle"], [(c.view, c.proj, c.width, c.height, vb) for c, vb in
+                                                         zip(cams, vbs)], pr.RenderOpts.make(counters=1), work, need)
+    st = pr.pr_get_stats(ctx.handle)
+    pr.pr_sync(ctx.handle)
+    tot = None
+    for c, vb in zip(cams, vbs):
+        ref, s = _oracle_frame(c3.built, c, c3.nb)
+        assert_vb_equal(vb.cpu().numpy().view(np.uint64), ref, c.width)
+        tot = s if tot is None else {k: (tot[k] + s[k] if not isinstance(s[k], list) else
+                                         [a + b for a, b in zip(tot[k], s[k])]) for k in s}
+    oracle_stats_match(st, tot)
