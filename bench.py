@@ -182,6 +182,56 @@ def kernel_hash():
     return h.hexdigest()
 
 
+def multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, plain_ms, steps, warmup):
+    """The same stereo step with both eyes in one multi-view launch, and both forms replayed from HIP graphs."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    need = pr.pr_views_work_bytes(cloud["handle"], len(cams))
+    work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    vlist = [(c.view, c.proj, c.width, c.height, vb) for c, vb in zip(cams, vbs)]
+
+    def frame_views():
+        pr.pr_render_views(ctx.handle, cloud["handle"], vlist, None, work, need)
+        for c, vb, fb in zip(cams, vbs, fbs):
+            pr.pr_resolve(ctx.handle, cloud["handle"], vb, c.width, c.height, 0xFF000000, fb)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        pr.pr_sync(ctx.handle)
+        return [a.elapsed_time(b) for a, b in ev]
+
+    mv = timed(frame_views)
+    res = {"launches": "one clear, one classify, one render launch for both eyes; resolve per eye",
+           "ms_per_step": round(float(np.mean(mv)), 4),
+           "gpts": round(processed / (float(np.mean(mv)) * 1e-3) / 1e9, 3),
+           "frame_ms_p50": round(float(np.percentile(mv, 50)), 4),
+           "frame_ms_p99": round(float(np.percentile(mv, 99)), 4),
+           "speedup_vs_plain": round(plain_ms / float(np.mean(mv)), 4)}
+    log(f"multi-view: {res}")
+    graphs = {}
+    for name, fn in (("plain", frame), ("multiview", frame_views)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            fn()
+        t = timed(g.replay)
+        graphs[name] = {"ms_per_step": round(float(np.mean(t)), 4),
+                        "gpts": round(processed / (float(np.mean(t)) * 1e-3) / 1e9, 3)}
+        del g
+    res["hip_graph"] = graphs
+    log(f"graphs: {graphs}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,7 +268,10 @@ def main():
     import paper_2204_01287_amd as pr
 
     wl = workload(args.workload, args.n)
-    ctx = pr.Context(0)
+    # everything runs on one side stream, so that frames can be captured into HIP graphs
+    main_stream = torch.cuda.Stream()
+    torch.cuda.set_stream(main_stream)
+    ctx = pr.Context(0, stream=main_stream)
     cloud = load_cloud(ctx, wl)
     cams = wl["cams"]
     vbs = [torch.empty(c.width * c.height, dtype=torch.int64, device="cuda") for c in cams]
@@ -301,6 +354,8 @@ def main():
                      "algorithmic_bytes_per_launch": [int(b) for b in alg_bytes],
                      "traffic": traffic},
     }
+    out["multiview"] = multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, ms_per_step,
+                                            args.steps, args.warmup)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl["n"]), args.cpu_seconds)
