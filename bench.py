@@ -232,6 +232,65 @@ def multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, plain
     return res
 
 
+def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
+    """Served workload: 8 resident terrain clouds (3.41e9 points), a seeded Poisson request stream with random
+    cameras and image sizes 640x480 / 1920x1080 / 3840x2160, admission by visibility + framebuffer bytes.
+    Continuous batching (grouped multi-view launches on 4 streams) against one view per launch on one stream:
+    latency at the offered rate, and capacity with every request arriving at once."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2204_01287_amd.serve import Request, Server
+
+    t0 = time.perf_counter()
+    clouds = []
+    for seed, n in synth.SERVED_CLOUDS:
+        c = load_cloud(ctx, dict(name=f"served_{seed}", seed=seed, n=n, morton=True, order=0))
+        pr.pr_cloud_drop_load_buffers(c["handle"])
+        for f in ("xyz", "rgba", "perm", "scratch"):
+            c["mem"][f] = None
+        torch.cuda.empty_cache()
+        clouds.append(c)
+    t_load = time.perf_counter() - t0
+    resident = sum(t.numel() for c in clouds for t in c["mem"].values() if t is not None)
+    log(f"served: {len(clouds)} clouds resident ({resident / 1e9:.1f} GB) after {t_load:.1f} s")
+    stream = synth.request_stream(5, nreq, rate, [s for s, _ in synth.SERVED_CLOUDS])
+    handles = [c["handle"] for c in clouds]
+    # processed points of every request (Table 2 definition), counted solo once
+    pts = []
+    need = pr.pr_views_work_bytes(handles[-1], 1)
+    work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    for a, ci, cam in stream:
+        vb = torch.empty(cam.width * cam.height, dtype=torch.int64, device="cuda")
+        pr.pr_render_views(ctx.handle, handles[ci], [(cam.view, cam.proj, cam.width, cam.height, vb)],
+                           pr.RenderOpts.make(counters=1), work, need)
+        pts.append(pr.pr_get_stats(ctx.handle)["points"])
+    total_pts = float(sum(pts))
+    out = {"workload": "8 terrain clouds 1e7..1e9 (3.41e9 points), Poisson requests, 640x480/1920x1080/3840x2160",
+           "requests": nreq, "rate_per_s": rate, "budget_bytes": budget, "resident_gb": round(resident / 1e9, 2),
+           "load_s": round(t_load, 1), "mean_processed_points": round(total_pts / nreq)}
+    modes = {"batched": dict(nstreams=4, max_group=64), "one_view_per_launch": dict(nstreams=1, max_group=1)}
+    for name, kw in modes.items():
+        for load in ("offered", "saturated"):
+            reqs = [Request(i, ci, cam, a if load == "offered" else 0.0) for i, (a, ci, cam) in enumerate(stream)]
+            srv = Server(handles, budget_bytes=budget, **kw)
+            done = srv.run(reqs)
+            srv.close()
+            lat = np.array([d.latency for d in done]) * 1e3
+            span = max(d.completed for d in done) - min(r.arrival for r in reqs)
+            out[f"{name}_{load}"] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                                     "gpts": round(total_pts / span / 1e9, 2), "span_s": round(span, 3),
+                                     "mean_group": round(float(np.mean([d.group for d in done])), 2)}
+            log(f"served {name} {load}: {out[f'{name}_{load}']}")
+    out["capacity_speedup"] = round(out["batched_saturated"]["gpts"] / out["one_view_per_launch_saturated"]["gpts"], 3)
+    for c in clouds:
+        pr.pr_cloud_free(c["handle"])
+        c["mem"].clear()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +301,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-mode leg")
+    ap.add_argument("--served-requests", type=int, default=1000)
+    ap.add_argument("--served-rate", type=float, default=500.0)
+    ap.add_argument("--served-budget", type=int, default=4 << 30, help="bytes of visibility + frame buffers in flight")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -356,11 +419,15 @@ def main():
     }
     out["multiview"] = multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, ms_per_step,
                                             args.steps, args.warmup)
+    pr.pr_cloud_free(cloud["handle"])
+    cloud["mem"].clear()
+    torch.cuda.empty_cache()
+    if not args.no_served:
+        out["served"] = served_leg(pr, ctx, args.served_requests, args.served_rate, args.served_budget)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl["n"]), args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    pr.pr_cloud_free(cloud["handle"])
     ctx.close()
 
 

@@ -31,6 +31,9 @@
  *     optional Morton sort; perm[] maps it back to input order).  Empty
  *     pixels hold PR_EMPTY.  Keys compare as unsigned 64-bit integers.
  *   - Limits: n < 2^32; 1 <= w, h <= 8192; batch sizes are multiples of 4.
+ *   - Contexts and streams: a built cloud may be rendered and resolved through
+ *     any context on its device (one context per HIP stream lets frames
+ *     overlap); pr_build_batches uses the context that loaded it.
  */
 #ifndef PTRASTER_H
 #define PTRASTER_H
@@ -176,10 +179,14 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
 pr_status pr_clear(pr_ctx* ctx, uint64_t* visbuf, uint32_t w, uint32_t h);
 
 /* Render one view (Sec. 3.2, 3.3): clears visbuf (uint64[h*w], device) to
- * PR_EMPTY (unless opts->accumulate), then every batch is culled or rendered at its precision level and
- * every visible point is combined into visbuf by 64-bit atomic minimum.
- * visbuf must be 16-byte aligned (PR_EINVAL otherwise).  Asynchronous.  PR_ENONFINITE for non-finite matrices, PR_ESTATE before
- * pr_build_batches. */
+ * PR_EMPTY (unless opts->accumulate), then every batch is culled or rendered
+ * at its precision level and every visible point is combined into visbuf by
+ * 64-bit atomic minimum.  visbuf must be 16-byte aligned (PR_EINVAL
+ * otherwise).  The frame's work area lives in the cloud's scratch buffer, so
+ * pr_render calls on one cloud must not overlap (keep them on one stream;
+ * overlapping frames use pr_render_views with work buffers of their own).
+ * Asynchronous.  PR_ENONFINITE for non-finite matrices, PR_ESTATE before
+ * pr_build_batches or after pr_cloud_drop_load_buffers. */
 pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16],
                     uint32_t w, uint32_t h, const pr_render_opts* opts, uint64_t* visbuf);
 
@@ -198,6 +205,14 @@ pr_status pr_sync(pr_ctx* ctx);
 
 /* Cloud facts: point count, batch count, batch size (0 before a build). */
 pr_status pr_cloud_info(const pr_cloud* cloud, uint64_t* n, uint64_t* nbatches, uint32_t* batch_size);
+
+/* After pr_build_batches: the cloud no longer uses its xyz, rgba, perm and
+ * scratch buffers, which the caller may then free; what stays is what
+ * rendering reads (low, med, high, colors, batches: 16 bytes per point plus
+ * 32 per batch).  Afterwards pr_render_views and pr_resolve work as before;
+ * pr_render (whose work area is the scratch buffer) and pr_build_batches
+ * fail with PR_ESTATE.  For many resident clouds (served mode). */
+pr_status pr_cloud_drop_load_buffers(pr_cloud* cloud);
 
 /* Free the host handle only; device buffers stay the caller's. */
 void pr_cloud_free(pr_cloud* cloud);

@@ -24,7 +24,7 @@ _STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "
 
 EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_load_points", "pr_build_batches",
             "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
-            "pr_views_work_bytes", "pr_render_views"]
+            "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers"]
 
 
 class PrError(RuntimeError):
@@ -84,13 +84,15 @@ lib.pr_render.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts)
 lib.pr_resolve.argtypes = [_P, _P, _P, _U32, _U32, _U32, _P]
 lib.pr_get_stats.argtypes = [_P, ctypes.POINTER(Stats)]
 lib.pr_views_work_bytes.argtypes = [_P, _U32, ctypes.POINTER(_U64)]
+lib.pr_cloud_drop_load_buffers.argtypes = [_P]
 lib.pr_render_views.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64]
 lib.pr_sync.argtypes = [_P]
 lib.pr_cloud_info.argtypes = [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U32)]
 lib.pr_cloud_free.argtypes = [_P]
 lib.pr_cloud_free.restype = None
 for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
-           "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views"):
+           "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views",
+           "pr_cloud_drop_load_buffers"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -160,6 +162,10 @@ def pr_render(ctx, cloud, view, proj, w: int, h: int, opts: RenderOpts | None, v
     p, pp = _mat16(proj)
     _check(lib.pr_render(ctx, cloud, vp, pp, w, h, ctypes.byref(opts) if opts is not None else None, _ptr(visbuf)),
            "pr_render")
+
+
+def pr_cloud_drop_load_buffers(cloud):
+    _check(lib.pr_cloud_drop_load_buffers(cloud), "pr_cloud_drop_load_buffers")
 
 
 def pr_views_work_bytes(cloud, nviews: int) -> int:
@@ -250,6 +256,12 @@ class DeviceCloud:
         pr_build_batches(ctx.handle, self.handle, batch_size, morton)
         self._src = None
         self.nb = pr_cloud_info(self.handle)[1]
+
+    def drop_load_buffers(self):
+        """Keep only what rendering reads; frees positions, input colours, permutation and scratch."""
+        pr_cloud_drop_load_buffers(self.handle)
+        for f in ("xyz", "rgba", "perm", "scratch"):
+            self.mem[f] = None
 
     def view(self, field: str, dtype, count: int):
         """A typed torch view of one buffer (e.g. view('low', torch.int32, n))."""

@@ -29,6 +29,7 @@ struct pr_cloud {
   uint32_t batch_size;
   int morton;
   int built;
+  int load_dropped;  // xyz, rgba, perm and scratch released by the caller: pr_render_views / pr_resolve only
   pr_cloud_bufs bufs;
 };
 
@@ -188,6 +189,7 @@ pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, ui
   c->batch_size = 0;
   c->morton = 0;
   c->built = 0;
+  c->load_dropped = 0;
   c->bufs = *bufs;
   *out = c;
   return PR_OK;
@@ -196,6 +198,7 @@ pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, ui
 pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton) {
   if (!ctx || !cloud) return fail(PR_EINVAL, "pr_build_batches: NULL argument");
   if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_build_batches: cloud belongs to another context");
+  if (cloud->load_dropped) return fail(PR_ESTATE, "pr_build_batches: the cloud's load buffers were released");
   pr_sizes need;
   if (pr_status s = sizes_for(cloud->n, batch_size, morton, &need)) return s;
   const pr_cloud_bufs& B = cloud->bufs;
@@ -261,7 +264,9 @@ pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, in
 pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16], uint32_t w,
                     uint32_t h, const pr_render_opts* opts, uint64_t* visbuf) {
   if (!ctx || !cloud || !view || !proj || !visbuf) return fail(PR_EINVAL, "pr_render: NULL argument");
-  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_render: cloud belongs to another context");
+  if (cloud->ctx->device != ctx->device) return fail(PR_EINVAL, "pr_render: cloud lives on another device");
+  if (cloud->load_dropped)
+    return fail(PR_ESTATE, "pr_render: the cloud's scratch was released (pr_cloud_drop_load_buffers); use pr_render_views");
   if (!cloud->built) return fail(PR_ESTATE, "pr_render: cloud is not built (call pr_build_batches)");
   if (pr_status s = check_dims(w, h)) return s;
   if (reinterpret_cast<uintptr_t>(visbuf) & 15u) return fail(PR_EINVAL, "pr_render: visbuf must be 16-byte aligned");
@@ -303,6 +308,14 @@ pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], co
   return PR_OK;
 }
 
+pr_status pr_cloud_drop_load_buffers(pr_cloud* cloud) {
+  if (!cloud) return fail(PR_EINVAL, "pr_cloud_drop_load_buffers: NULL argument");
+  if (!cloud->built) return fail(PR_ESTATE, "pr_cloud_drop_load_buffers: cloud is not built");
+  cloud->load_dropped = 1;
+  cloud->bufs.xyz = cloud->bufs.rgba = cloud->bufs.perm = cloud->bufs.scratch = nullptr;
+  return PR_OK;
+}
+
 pr_status pr_views_work_bytes(const pr_cloud* cloud, uint32_t nviews, uint64_t* out) {
   if (!cloud || !out) return fail(PR_EINVAL, "pr_views_work_bytes: NULL argument");
   if (nviews < 1 || nviews > PR_MAX_VIEWS) return fail(PR_ERANGE, "pr_views_work_bytes: nviews %u not in 1..%d", nviews, PR_MAX_VIEWS);
@@ -314,7 +327,7 @@ pr_status pr_views_work_bytes(const pr_cloud* cloud, uint32_t nviews, uint64_t* 
 pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
                           const pr_render_opts* opts, void* work, uint64_t work_bytes) {
   if (!ctx || !cloud || !views || !work) return fail(PR_EINVAL, "pr_render_views: NULL argument");
-  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_render_views: cloud belongs to another context");
+  if (cloud->ctx->device != ctx->device) return fail(PR_EINVAL, "pr_render_views: cloud lives on another device");
   if (!cloud->built) return fail(PR_ESTATE, "pr_render_views: cloud is not built (call pr_build_batches)");
   if (nviews < 1 || nviews > PR_MAX_VIEWS) return fail(PR_ERANGE, "pr_render_views: nviews %u not in 1..%d", nviews, PR_MAX_VIEWS);
   if (reinterpret_cast<uintptr_t>(work) & 255u) return fail(PR_EINVAL, "pr_render_views: work must be 256-byte aligned");
@@ -407,7 +420,7 @@ pr_status pr_clear(pr_ctx* ctx, uint64_t* visbuf, uint32_t w, uint32_t h) {
 pr_status pr_resolve(pr_ctx* ctx, const pr_cloud* cloud, const uint64_t* visbuf, uint32_t w, uint32_t h,
                      uint32_t clear_rgba, uint32_t* rgba_out) {
   if (!ctx || !cloud || !visbuf || !rgba_out) return fail(PR_EINVAL, "pr_resolve: NULL argument");
-  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_resolve: cloud belongs to another context");
+  if (cloud->ctx->device != ctx->device) return fail(PR_EINVAL, "pr_resolve: cloud lives on another device");
   if (!cloud->built) return fail(PR_ESTATE, "pr_resolve: cloud is not built");
   if (pr_status s = check_dims(w, h)) return s;
   if (pr_status s = set_device(ctx)) return s;

@@ -202,3 +202,35 @@ def random_camera(rng: np.random.Generator, width: int, height: int, inside: boo
     up = (0.0, 0.0, 1.0) if abs((target - eye)[2]) < 0.95 * np.linalg.norm(target - eye) else (0.0, 1.0, 0.0)
     fovy = float(rng.uniform(30.0, 100.0))
     return camera(eye, target, up, fovy, width, height, 0.1, 10.0 * ext)
+
+
+# ------------------------------------------------------------- served mode
+# Resident clouds of the served workload: (terrain seed, points).
+SERVED_CLOUDS = [(1, 10_000_000), (2, 50_000_000), (3, 100_000_000), (4, 250_000_000), (5, 500_000_000),
+                 (6, 500_000_000), (7, 1_000_000_000), (8, 1_000_000_000)]
+SERVED_SIZES = [(640, 480), (1920, 1080), (3840, 2160)]
+
+
+def served_camera(rng: np.random.Generator, seed: int, width: int, height: int) -> Camera:
+    """A camera over the terrain of `seed`: uniform (x, y) in [0, 1000]^2, altitude U(20, 400) m above the ground
+    there, yaw U(0, 2 pi), pitch U(-60, -10) deg, fovy 60 deg, near 0.5, far 5000."""
+    x, y = rng.uniform(0.0, 1000.0, 2)
+    alt = rng.uniform(20.0, 400.0)
+    yaw = rng.uniform(0.0, 2.0 * math.pi)
+    pitch = math.radians(rng.uniform(-60.0, -10.0))
+    eye = np.array([x, y, terrain_height(seed, float(x), float(y)) + alt])
+    fwd = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+    return camera(eye, eye + fwd, (0.0, 0.0, 1.0), 60.0, width, height, 0.5, 5000.0)
+
+
+def request_stream(seed: int, n: int, rate: float, cloud_seeds, sizes=SERVED_SIZES):
+    """n requests of a Poisson stream at `rate` per second: (arrival s, cloud index, Camera), in arrival order;
+    uniform cloud and image size, camera by served_camera over that cloud's terrain."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    out = []
+    for i in range(n):
+        c = int(rng.integers(len(cloud_seeds)))
+        w, h = sizes[int(rng.integers(len(sizes)))]
+        out.append((float(arrivals[i]), c, served_camera(rng, cloud_seeds[c], w, h)))
+    return out

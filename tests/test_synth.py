@@ -62,3 +62,13 @@ def test_terrain_gather_matches_whole_cloud():
         assert np.array_equal(x, xyz[idx]) and np.array_equal(c, rgba[idx])
     with pytest.raises(RuntimeError):
         synth.terrain_gather(6, n, np.array([n], np.uint32))
+
+
+def test_request_stream_is_seeded_and_poisson():
+    a = synth.request_stream(3, 400, 500.0, [1, 2, 3])
+    b = synth.request_stream(3, 400, 500.0, [1, 2, 3])
+    assert [(x, c, cam.width) for x, c, cam in a] == [(x, c, cam.width) for x, c, cam in b]
+    assert all(np.array_equal(p[2].view, q[2].view) for p, q in zip(a, b))
+    t = np.array([x for x, _, _ in a])
+    assert np.all(np.diff(t) > 0) and 0.6 < t[-1] < 1.0  # 400 arrivals at 500/s take about 0.8 s
+    assert {cam.width for _, _, cam in a} == {640, 1920, 3840} and {c for _, c, _ in a} == {0, 1, 2}
