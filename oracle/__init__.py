@@ -76,6 +76,9 @@ def _lib_():
         L.or_render.argtypes = [P, U64, P, U64, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts), P,
                                 ctypes.POINTER(Stats)]
         L.or_resolve.argtypes = [P, U64, P, U64, U32, P]
+        L.or_accumulate.argtypes = [P, U64, P, U64, P, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts),
+                                    ctypes.c_float, P, P]
+        L.or_resolve_hqs.argtypes = [P, U64, U32, P]
         _lib = L
     return _lib
 
@@ -209,4 +212,29 @@ def resolve(vb, colors, clear_rgba: int = 0):
     colors = _c(colors, np.uint32)
     fb = np.empty(vb.shape[0], np.uint32)
     _lib_().or_resolve(_p(vb), vb.shape[0], _p(colors), colors.shape[0], clear_rgba, _p(fb))
+    return fb
+
+
+def accumulate(built: Built, view, proj, w: int, h: int, vb, window: float = 1.01, o: Opts | None = None,
+               batch_ids=None, colors=None):
+    """High-quality shading sums (Sec. 3.6): uint64[2*h*w] (R + G<<32, B + count<<32 per pixel) of the points
+    within fl32(closest depth * window) of each pixel's closest point; vb is the render of the same view."""
+    o = o or opts()
+    view = _c(view, np.float32)
+    proj = _c(proj, np.float32)
+    vb = _c(vb, np.uint64)
+    cols = _c(built.colors if colors is None else colors, np.uint32)
+    acc = np.zeros(2 * w * h, np.uint64)
+    ids = None if batch_ids is None else _c(batch_ids, np.uint64)
+    _lib_().or_accumulate(_p(built.batches), built.batches.shape[0], _p(ids), 0 if ids is None else ids.shape[0],
+                          _p(built.low), _p(built.med), _p(built.high), _p(cols), _p(view), _p(proj), w, h,
+                          ctypes.byref(o), float(np.float32(window)), _p(vb), _p(acc))
+    return acc
+
+
+def resolve_hqs(acc, clear_rgba: int = 0):
+    """The averaged colour per pixel (rounded to nearest, alpha 255), clear_rgba where no point joined."""
+    acc = _c(acc, np.uint64)
+    fb = np.empty(acc.shape[0] // 2, np.uint32)
+    _lib_().or_resolve_hqs(_p(acc), fb.shape[0], clear_rgba, _p(fb))
     return fb

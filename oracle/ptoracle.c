@@ -21,6 +21,8 @@
  *   O7 per-point raster  -- Sec. 3.2 point rasterization listing: project,
  *                           64-bit key (depth bits << 32 | index), atomicMin.
  *   O8 resolve           -- Sec. 3.3 visibility buffer: index -> colour.
+ *   O10 shading          -- Sec. 3.6 high-quality shading: colour sums and
+ *                           counts within a depth window, then the average.
  *
  * Arithmetic rules (both sides follow the same written definition):
  *   - binary64 steps use plain + - * / with no fused multiply-add
@@ -66,6 +68,11 @@ static inline uint32_t f32_bits(float f) {
   uint32_t u;
   memcpy(&u, &f, 4);
   return u;
+}
+static inline float f32_from_bits(uint32_t u) {
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
 }
 
 /* Order used for bounding boxes: IEEE 754 totalOrder restricted to finite
@@ -356,13 +363,44 @@ void or_decide(const double Pm[3][4], const or_batch* B, uint32_t w, uint32_t h,
  *  key: (float bits of hw) << 32 | point index (Sec. 3.2 listing; hw > 0,
  *      so the bits order like the values); vb[p] = min(vb[p], key).
  * If batch_ids is non-NULL only those batches are rendered (any order). */
+/* O7 steps 1-4 for point i of a batch with decision d: decode at the batch's
+ * level, project with the three fmaf chains, reject unless hw > 0 and the
+ * point is inside the image; the pixel is the exact floor of hx/hw, hy/hw
+ * (floor of the binary64 quotient of two binary32 values, which is exact for
+ * quotients below 2^26).  Returns 1 and (hw, pixel index) for a drawn point. */
+static int or_point(const or_decision* d, const uint32_t* low, const uint32_t* med, const uint32_t* high,
+                    uint64_t i, uint32_t w, uint32_t h, float* hw_out, uint64_t* p_out) {
+  float XYZ[3];
+  for (int a = 0; a < 3; ++a) {
+    uint32_t lo = (low[i] >> (10 * a)) & 1023u;
+    uint32_t F;
+    if (d->level == 10) {
+      F = lo;
+    } else if (d->level == 20) {
+      F = (lo << 10) | ((med[i] >> (10 * a)) & 1023u);
+    } else {
+      F = (lo << 20) | (((med[i] >> (10 * a)) & 1023u) << 10) | ((high[i] >> (10 * a)) & 1023u);
+    }
+    XYZ[a] = (float)F;
+  }
+  float hx = fmaf(d->P[0][2], XYZ[2], fmaf(d->P[0][1], XYZ[1], fmaf(d->P[0][0], XYZ[0], d->t[0])));
+  float hy = fmaf(d->P[1][2], XYZ[2], fmaf(d->P[1][1], XYZ[1], fmaf(d->P[1][0], XYZ[0], d->t[1])));
+  float hw = fmaf(d->P[2][2], XYZ[2], fmaf(d->P[2][1], XYZ[1], fmaf(d->P[2][0], XYZ[0], d->t[2])));
+  if (!(hw > 0.0f)) return 0;
+  double dx = (double)hx, dy = (double)hy, dw = (double)hw;
+  if (!(dx >= 0.0 && dx < (double)w * dw && dy >= 0.0 && dy < (double)h * dw)) return 0;
+  uint64_t px = (uint64_t)floor(dx / dw), py = (uint64_t)floor(dy / dw);
+  *hw_out = hw;
+  *p_out = py * w + px;
+  return 1;
+}
+
 void or_render(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, uint64_t nids,
                const uint32_t* low, const uint32_t* med, const uint32_t* high, const float view[16],
                const float proj[16], uint32_t w, uint32_t h, const or_opts* o, uint64_t* vb,
                or_stats* st) {
   double Pm[3][4];
   or_frame_matrix(view, proj, w, h, Pm);
-  double Wd = (double)w, Hd = (double)h;
   uint64_t n_iter = batch_ids ? nids : nb;
   if (st) memset(st, 0, sizeof *st);
   for (uint64_t it = 0; it < n_iter; ++it) {
@@ -382,28 +420,10 @@ void or_render(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, 
       st->level_points[li] += B->count;
     }
     for (uint64_t i = B->first; i < (uint64_t)B->first + B->count; ++i) {
-      float XYZ[3];
-      for (int a = 0; a < 3; ++a) {
-        uint32_t lo = (low[i] >> (10 * a)) & 1023u;
-        uint32_t F;
-        if (d.level == 10) {
-          F = lo;
-        } else if (d.level == 20) {
-          F = (lo << 10) | ((med[i] >> (10 * a)) & 1023u);
-        } else {
-          F = (lo << 20) | (((med[i] >> (10 * a)) & 1023u) << 10) | ((high[i] >> (10 * a)) & 1023u);
-        }
-        XYZ[a] = (float)F;
-      }
-      float hx = fmaf(d.P[0][2], XYZ[2], fmaf(d.P[0][1], XYZ[1], fmaf(d.P[0][0], XYZ[0], d.t[0])));
-      float hy = fmaf(d.P[1][2], XYZ[2], fmaf(d.P[1][1], XYZ[1], fmaf(d.P[1][0], XYZ[0], d.t[1])));
-      float hw = fmaf(d.P[2][2], XYZ[2], fmaf(d.P[2][1], XYZ[1], fmaf(d.P[2][0], XYZ[0], d.t[2])));
-      if (!(hw > 0.0f)) continue;
-      double dx = (double)hx, dy = (double)hy, dw = (double)hw;
-      if (!(dx >= 0.0 && dx < Wd * dw && dy >= 0.0 && dy < Hd * dw)) continue;
-      uint64_t px = (uint64_t)floor(dx / dw), py = (uint64_t)floor(dy / dw);
+      float hw;
+      uint64_t p;
+      if (!or_point(&d, low, med, high, i, w, h, &hw, &p)) continue;
       uint64_t key = ((uint64_t)f32_bits(hw) << 32) | (uint64_t)i;
-      uint64_t p = py * w + px;
       if (key < vb[p]) vb[p] = key;
     }
   }
@@ -427,5 +447,59 @@ void or_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint6
   for (uint64_t p = 0; p < npix; ++p) {
     uint32_t idx = (uint32_t)(vb[p] & 0xFFFFFFFFull);
     fb[p] = (vb[p] == OR_EMPTY || idx >= ncolors) ? clear_rgba : colors[idx];
+  }
+}
+
+/* ------------------------------------------------------- high-quality shading */
+/* Sec. 3.6: the colours of the points within a depth range behind each
+ * pixel's closest point are summed with a counter, and a final pass divides.
+ * Reading taken here:
+ *   - the closest depth of pixel p is the depth of its visibility-buffer key,
+ *     hw_min = bits (vb[p] >> 32) as binary32 (vb from or_render, same opts);
+ *   - point i (drawn by O7 at pixel p) joins iff hw_i <= fl32(hw_min * window),
+ *     one binary32 multiplication (window >= 1; 1.01 = "1 % behind");
+ *   - the sums are the paper's two 64-bit words per pixel holding four 32-bit
+ *     fields: acc[2p] += R + G * 2^32, acc[2p + 1] += B + 2^32 (count), with
+ *     R, G, B the low three bytes of the point's colour; additions wrap
+ *     modulo 2^64 (exact while a pixel's sums stay below 2^32). */
+void or_accumulate(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, uint64_t nids,
+                   const uint32_t* low, const uint32_t* med, const uint32_t* high, const uint32_t* colors,
+                   const float view[16], const float proj[16], uint32_t w, uint32_t h, const or_opts* o,
+                   float window, const uint64_t* vb, uint64_t* acc) {
+  double Pm[3][4];
+  or_frame_matrix(view, proj, w, h, Pm);
+  uint64_t n_iter = batch_ids ? nids : nb;
+  for (uint64_t it = 0; it < n_iter; ++it) {
+    const or_batch* B = &batches[batch_ids ? batch_ids[it] : it];
+    or_decision d;
+    or_decide(Pm, B, w, h, o, &d);
+    if (d.culled) continue;
+    for (uint64_t i = B->first; i < (uint64_t)B->first + B->count; ++i) {
+      float hw;
+      uint64_t p;
+      if (!or_point(&d, low, med, high, i, w, h, &hw, &p)) continue;
+      float hw_min = f32_from_bits((uint32_t)(vb[p] >> 32));
+      float thr = hw_min * window;
+      if (!(hw <= thr)) continue;
+      uint32_t c = colors[i];
+      acc[2 * p] += (uint64_t)(c & 255u) + ((uint64_t)((c >> 8) & 255u) << 32);
+      acc[2 * p + 1] += (uint64_t)((c >> 16) & 255u) + (1ull << 32);
+    }
+  }
+}
+
+/* The average: each channel (sum + count / 2) / count (rounded to nearest,
+ * halves up), alpha 255; pixels with no point get the clear colour. */
+void or_resolve_hqs(const uint64_t* acc, uint64_t npix, uint32_t clear_rgba, uint32_t* fb) {
+  for (uint64_t p = 0; p < npix; ++p) {
+    uint64_t n = acc[2 * p + 1] >> 32;
+    if (n == 0) {
+      fb[p] = clear_rgba;
+      continue;
+    }
+    uint64_t r = ((acc[2 * p] & 0xFFFFFFFFull) + n / 2) / n;
+    uint64_t g = ((acc[2 * p] >> 32) + n / 2) / n;
+    uint64_t b = ((acc[2 * p + 1] & 0xFFFFFFFFull) + n / 2) / n;
+    fb[p] = (uint32_t)r | ((uint32_t)g << 8) | ((uint32_t)b << 16) | (255u << 24);
   }
 }

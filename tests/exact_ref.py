@@ -151,3 +151,35 @@ def brute_force(xyz_sorted, batch_size, view, proj, w, h, precision=0, t10=500.0
             if pix not in out or key < out[pix]:
                 out[pix] = key
     return out, levels
+
+
+def brute_force_hqs(xyz_sorted, colors, batch_size, view, proj, w, h, window, precision=0):
+    """High-quality shading sums by definition: dict pixel -> (R + G*2^32, B + count*2^32) mod 2^64 over the
+    points within round32(closest hw * round32(window)) of each pixel's closest point."""
+    n = len(xyz_sorted)
+    Pm = frame_matrix(view, proj, w, h)
+    hits = {}
+    for b0 in range(0, n, batch_size):
+        pts = xyz_sorted[b0:b0 + batch_size]
+        bmin = [min(float(p[a]) for p in pts) for a in range(3)]
+        bmax = [max(float(p[a]) for p in pts) for a in range(3)]
+        k, P, t = batch_level_and_fold(Pm, bmin, bmax, w, h, precision)
+        for j, p in enumerate(pts):
+            r = point_key(b0 + j, p, bmin, bmax, k, P, t, w, h)
+            if r is None:
+                continue
+            pix, key = r
+            hw = Fraction(struct.unpack("<f", struct.pack("<I", key >> 32))[0])
+            hits.setdefault(pix, []).append((hw, int(colors[b0 + j])))
+    win = f32(window)
+    out = {}
+    M = 1 << 64
+    for pix, lst in hits.items():
+        thr = round32(min(hw for hw, _ in lst) * win)
+        a0 = a1 = 0
+        for hw, c in lst:
+            if hw <= thr:
+                a0 = (a0 + (c & 255) + (((c >> 8) & 255) << 32)) % M
+                a1 = (a1 + ((c >> 16) & 255) + (1 << 32)) % M
+        out[pix] = (a0, a1)
+    return out

@@ -409,3 +409,70 @@ def test_resolve_foreign_index_gives_clear():
     colors = np.arange(10, dtype=np.uint32) + 100
     vb = np.array([3, 10, 0xFFFFFFFF, (0x40000000 << 32) | 9], np.uint64)
     assert oracle.resolve(vb, colors, 7).tolist() == [103, 7, 7, 109]
+
+
+# ------------------------------------------------------- high-quality shading (Sec. 3.6)
+def _worked_built():
+    g = _gold()
+    xyz = np.array(g["points"], np.float32)
+    cols = np.array([_hex(c) for c in g["colors"]], np.uint32)
+    B = oracle.build_cloud(xyz, cols, g["batch_size"], morton=False)
+    view, proj = np.array(g["view"], np.float32), np.array(g["proj"], np.float32)
+    return g, B, view, proj
+
+
+@pytest.mark.parametrize("window", ["1.01", "1.3"])
+def test_hqs_worked_example(window):
+    """Hand-derived sums and averages (tests/golden/worked_example.json, hqs)."""
+    g, B, view, proj = _worked_built()
+    w, h = g["width"], g["height"]
+    vb, _ = oracle.render(B, view, proj, w, h)
+    acc = oracle.accumulate(B, view, proj, w, h, vb, window=float(window))
+    want = g["hqs"][window]
+    covered = {int(p) for p in np.nonzero(acc[1::2] >> np.uint64(32))[0]}
+    assert covered == {int(p) for p in want["acc"]}
+    for p, (a0, a1) in want["acc"].items():
+        assert (int(acc[2 * int(p)]), int(acc[2 * int(p) + 1])) == (a0, a1)
+    fb = oracle.resolve_hqs(acc, 0)
+    for p in range(w * h):
+        assert int(fb[p]) == (_hex(want["fb"][str(p)]) if str(p) in want["fb"] else 0)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_hqs_matches_exact_bruteforce(seed):
+    """Exact-rational reference: every drawn point's hw, the window threshold rounded once to binary32, the
+    packed sums modulo 2^64."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(60, 300))
+    S = int(rng.choice([4, 8, 16]))
+    xyz = _tiny_cloud(rng, n)
+    rgba = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    B = oracle.build_cloud(xyz, rgba, S, morton=bool(seed % 2))
+    w, h = int(rng.integers(8, 30)), int(rng.integers(8, 30))
+    cam = synth.random_camera(rng, w, h, inside=bool(seed % 3 == 0), box=((0, 0, 0), (10, 10, 10)))
+    for window, prec in [(1.0, 0), (1.01, 0), (1.2, 10), (3.0, 30)]:
+        o = oracle.opts(precision=prec)
+        vb, _ = oracle.render(B, cam.view, cam.proj, w, h, o)
+        acc = oracle.accumulate(B, cam.view, cam.proj, w, h, vb, window=window, o=o)
+        want = exact_ref.brute_force_hqs(B.xyz.tolist(), B.colors.tolist(), S, cam.view.tolist(), cam.proj.tolist(),
+                                         w, h, window, prec)
+        got = {p: (int(acc[2 * p]), int(acc[2 * p + 1])) for p in range(w * h) if acc[2 * p + 1] != 0}
+        assert got == want
+
+
+def test_hqs_window_one_keeps_the_ties_at_the_closest_depth():
+    g, B, view, proj = _worked_built()
+    vb, _ = oracle.render(B, view, proj, g["width"], g["height"])
+    acc = oracle.accumulate(B, view, proj, g["width"], g["height"], vb, window=1.0)
+    counts = {int(p): int(acc[2 * p + 1] >> np.uint64(32)) for p in np.nonzero(acc[1::2])[0]}
+    assert counts == {18: 4, 20: 2, 63: 1}  # four points share depth 6, two share depth 4
+
+
+def test_hqs_resolve_rounds_to_nearest():
+    H = 1 << 32
+    acc = np.array([3 + 5 * H, 7 + 2 * H,      # R 3/2 -> 2 (half up), G 5/2 -> 3, B 7/2 -> 4
+                    0, 0,                       # nothing joined: clear colour
+                    255 * 3 + 0 * H, 1 + 3 * H],  # R 255, G 0, B 1/3 -> 0
+                   np.uint64)
+    fb = oracle.resolve_hqs(acc, 0x12345678)
+    assert fb.tolist() == [0xFF040302, 0x12345678, 0xFF0000FF]
