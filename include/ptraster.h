@@ -190,6 +190,23 @@ pr_status pr_clear(pr_ctx* ctx, uint64_t* visbuf, uint32_t w, uint32_t h);
 pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16],
                     uint32_t w, uint32_t h, const pr_render_opts* opts, uint64_t* visbuf);
 
+/* High-quality shading of one view (Sec. 3.6): renders the view into visbuf
+ * exactly as pr_render (the closest depth per pixel), then every drawn point
+ * whose w is within the depth window of its pixel's closest point,
+ *   hw <= fl32(w_closest * window)   (binary32 product; window >= 1, e.g.
+ *                                     1.01 = "1 % behind the closest point"),
+ * adds its colour and a count to accum (uint64[2*h*w], device, 16-byte
+ * aligned, zeroed by this call): accum[2p] += R + G * 2^32, accum[2p+1] +=
+ * B + 2^32, with R, G, B the low three bytes of the colour (additions wrap
+ * mod 2^64, exact while a pixel's sums stay below 2^32).  Finally
+ * rgba_out[p] (uint32[h*w], 16-byte aligned) = the rounded average
+ * (sum + n/2) / n per channel with alpha 255, or clear_rgba where no point
+ * landed.  opts->accumulate must be 0.  Asynchronous; uses the cloud's
+ * scratch like pr_render.  PR_EINVAL for a window below 1 or not finite. */
+pr_status pr_render_hqs(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16],
+                        uint32_t w, uint32_t h, const pr_render_opts* opts, float window, uint64_t* visbuf,
+                        uint64_t* accum, uint32_t clear_rgba, uint32_t* rgba_out);
+
 /* Resolve (Sec. 3.3): rgba_out[p] = colors[VB[p] & 0xFFFFFFFF], or
  * clear_rgba where VB[p] == PR_EMPTY (or holds an index >= n, which a buffer
  * rendered from this cloud never does).  visbuf and rgba_out (uint32[h*w])

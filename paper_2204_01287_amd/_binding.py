@@ -24,7 +24,7 @@ _STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "
 
 EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_load_points", "pr_build_batches",
             "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
-            "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers"]
+            "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers", "pr_render_hqs"]
 
 
 class PrError(RuntimeError):
@@ -85,6 +85,7 @@ lib.pr_resolve.argtypes = [_P, _P, _P, _U32, _U32, _U32, _P]
 lib.pr_get_stats.argtypes = [_P, ctypes.POINTER(Stats)]
 lib.pr_views_work_bytes.argtypes = [_P, _U32, ctypes.POINTER(_U64)]
 lib.pr_cloud_drop_load_buffers.argtypes = [_P]
+lib.pr_render_hqs.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts), ctypes.c_float, _P, _P, _U32, _P]
 lib.pr_render_views.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64]
 lib.pr_sync.argtypes = [_P]
 lib.pr_cloud_info.argtypes = [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U32)]
@@ -92,7 +93,7 @@ lib.pr_cloud_free.argtypes = [_P]
 lib.pr_cloud_free.restype = None
 for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
            "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views",
-           "pr_cloud_drop_load_buffers"):
+           "pr_cloud_drop_load_buffers", "pr_render_hqs"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -183,6 +184,14 @@ def pr_render_views(ctx, cloud, views, opts: RenderOpts | None, work, work_bytes
         arr[i].w, arr[i].h, arr[i].visbuf = w, h, _ptr(vb)
     _check(lib.pr_render_views(ctx, cloud, arr, len(views), ctypes.byref(opts) if opts is not None else None,
                                _ptr(work), work_bytes), "pr_render_views")
+
+
+def pr_render_hqs(ctx, cloud, view, proj, w: int, h: int, opts: RenderOpts | None, window: float, visbuf, accum,
+                  clear_rgba: int, rgba_out):
+    v, vp = _mat16(view)
+    p, pp = _mat16(proj)
+    _check(lib.pr_render_hqs(ctx, cloud, vp, pp, w, h, ctypes.byref(opts) if opts is not None else None, window,
+                             _ptr(visbuf), _ptr(accum), clear_rgba & 0xFFFFFFFF, _ptr(rgba_out)), "pr_render_hqs")
 
 
 def pr_resolve(ctx, cloud, visbuf, w: int, h: int, clear_rgba: int, rgba_out):

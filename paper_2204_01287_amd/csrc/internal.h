@@ -60,6 +60,10 @@ struct RenderArgs {
   int32_t precision, cull, counters;
   float t10, t20;
   uint32_t grid;    // persistent render workgroups
+  // high-quality shading pass only
+  const uint32_t* colors;
+  uint64_t* accum;  // two words per pixel
+  float window;
 };
 
 // ---- several views in one launch
@@ -127,6 +131,11 @@ hipError_t launch_render_views(const RenderViewsArgs& a, uint64_t max_runs, int 
 uint32_t render_views_grid(int device);
 hipError_t launch_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint64_t ncolors,
                           uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
+// high-quality shading: zero the sums, the shading pass over the live batches of
+// the last launch_render, the averaging resolve
+hipError_t launch_accumulate(const RenderArgs& a, hipStream_t s);
+uint32_t accum_grid(int device);
+hipError_t launch_resolve_hqs(const uint64_t* accum, uint64_t npix, uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
 
 // ---- load-time build (kern_build.hip)
 struct SortScratch {

@@ -96,6 +96,10 @@ struct Loop {
   uint32_t tw, th;  // tile rectangle size (tiled batches)
   uint32_t tw8;     // tile row pitch in bytes
   uint64_t* vb;
+  // high-quality shading pass only
+  float window;     // depth window factor
+  uint64_t* acc;    // global sums, two words per pixel
+  float* thr;       // LDS tile of thresholds fl32(closest depth * window)
 };
 
 // Projection of one decoded point (the three fmaf chains, fixed order).
@@ -147,12 +151,67 @@ __device__ __forceinline__ uint64_t make_key(float hw, uint32_t idx) {
 
 struct Words {
   uint4 l, m, h;
+  uint4 c;  // colours (shading pass)
 };
 
-// Four consecutive points of one lane.
+// Shading sums of one colour: R + G << 32 and B + 1 << 32 (four 32-bit fields
+// in two 64-bit words, Sec. 3.6).
+__device__ __forceinline__ uint64_t sum_rg(uint32_t c) {
+  return (uint64_t)(c & 255u) | ((uint64_t)((c >> 8) & 255u) << 32);
+}
+__device__ __forceinline__ uint64_t sum_bn(uint32_t c) { return (uint64_t)((c >> 16) & 255u) | (1ull << 32); }
+
+// Shading pass, four consecutive points of one lane: a drawn point joins its
+// pixel's sums iff hw <= fl32(closest depth * window).  Tiled batches add into
+// the LDS sums (tile) behind the LDS threshold tile; others read the closest
+// depth from the visibility buffer and add into the global sums.
 template <int K, int CLS, bool TILED>
+__device__ __forceinline__ void four_points_acc(const Loop& L, uint64_t* tile, const Words& w, uint32_t nvalid) {
+  const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
+  const uint32_t Mw[4] = {w.m.x, w.m.y, w.m.z, w.m.w};
+  const uint32_t Hw[4] = {w.h.x, w.h.y, w.h.z, w.h.w};
+  const uint32_t Cw[4] = {w.c.x, w.c.y, w.c.z, w.c.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float X, Y, Z;
+    decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
+    const Proj p = project(L, X, Y, Z);
+    bool ok = (uint32_t)j < nvalid;
+    if constexpr (CLS != CLS_INSIDE) ok = ok && visible(L, p);
+    uint32_t px, py;
+    if constexpr (CLS == CLS_SLOW)
+      pixel_exact(p, px, py);
+    else
+      pixel_fast(p, L.cx, L.cy, px, py);
+    if constexpr (TILED) {
+      const uint32_t e = __umul24(py, L.tw) + px;
+      if (ok && p.hw <= L.thr[e]) {
+        __hip_atomic_fetch_add(&tile[2 * e], sum_rg(Cw[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&tile[2 * e + 1], sum_bn(Cw[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    } else {
+      ok = ok && (px < L.W) && (py < L.H);
+      const uint32_t off = __umul24(py, L.W) + px;
+      if (ok) {
+        const uint64_t k = __hip_atomic_load(L.vb + off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p.hw <= __uint_as_float((uint32_t)(k >> 32)) * L.window) {
+          __hip_atomic_fetch_add(L.acc + 2 * (uint64_t)off, sum_rg(Cw[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(L.acc + 2 * (uint64_t)off + 1, sum_bn(Cw[j]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+  }
+}
+
+// Four consecutive points of one lane.
+template <int K, int CLS, bool TILED, bool ACC = false>
 __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const Words& w, uint32_t i0,
                                             uint32_t nvalid, uint32_t& natom) {
+  if constexpr (ACC) {
+    four_points_acc<K, CLS, TILED>(L, tile, w, nvalid);
+    return;
+  }
   const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
   const uint32_t Mw[4] = {w.m.x, w.m.y, w.m.z, w.m.w};
   const uint32_t Hw[4] = {w.h.x, w.h.y, w.h.z, w.h.w};
@@ -242,9 +301,10 @@ struct Streams {
   const uint32_t* low;
   const uint32_t* med;
   const uint32_t* high;
+  const uint32_t* colors;  // shading pass only
 };
 
-template <int K>
+template <int K, bool ACC = false>
 __device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, uint32_t g, uint32_t lane) {
   const uint32_t q = first / 4 + g * 64 + lane;  // first is a multiple of 4
   Words w;
@@ -253,13 +313,15 @@ __device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, ui
   else w.m = make_uint4(0, 0, 0, 0);
   if constexpr (K == 30) w.h = reinterpret_cast<const uint4*>(a.high)[q];
   else w.h = make_uint4(0, 0, 0, 0);
+  if constexpr (ACC) w.c = reinterpret_cast<const uint4*>(a.colors)[q];
+  else w.c = make_uint4(0, 0, 0, 0);
   return w;
 }
 
 // The points of one batch, split over the workgroup's waves: wave w takes the
 // groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
 // 16-byte load per word).  Wave 0 also takes the ragged tail.
-template <int K, int CLS, bool TILED>
+template <int K, int CLS, bool TILED, bool ACC = false>
 __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
                               uint32_t wave, uint32_t lane, uint32_t& natom) {
   const uint32_t ngrp = count >> 8;
@@ -277,7 +339,7 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
 #pragma unroll
     for (int d = 0; d < PREFETCH; ++d) {
       gi[d] = wave + d * WAVES;
-      R[d] = load_group<K>(a, first, min(gi[d], glast), lane);
+      R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
       // keep the initial loads in the order of their use, the order the
       // loop reissues them in: the loop's waits then count PREFETCH - 1
       // younger loads on every path
@@ -287,10 +349,10 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
 #pragma unroll
       for (int d = 0; d < PREFETCH; ++d) {
         const uint32_t g = gi[d];
-        four_points<K, CLS, TILED>(L, tile, R[d], first + min(g, glast) * 256 + lane * 4, g <= glast ? 4u : 0u,
-                                   natom);
+        four_points<K, CLS, TILED, ACC>(L, tile, R[d], first + min(g, glast) * 256 + lane * 4,
+                                        g <= glast ? 4u : 0u, natom);
         gi[d] = g + PREFETCH * WAVES;
-        R[d] = load_group<K>(a, first, min(gi[d], glast), lane);
+        R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
       }
     }
   }
@@ -298,20 +360,22 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
   if (rem && wave == 0) {  // ragged tail of the batch: scalar loads, per-point bounds
     const uint32_t j0 = ngrp * 256 + lane * 4;
     const uint32_t nv = j0 < count ? min(4u, count - j0) : 0u;
-    uint32_t l[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0}, h[4] = {0, 0, 0, 0};
+    uint32_t l[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0}, h[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if ((uint32_t)j < nv) {
         l[j] = a.low[first + j0 + j];
         if constexpr (K >= 20) m[j] = a.med[first + j0 + j];
         if constexpr (K == 30) h[j] = a.high[first + j0 + j];
+        if constexpr (ACC) c[j] = a.colors[first + j0 + j];
       }
     }
     Words t;
     t.l = make_uint4(l[0], l[1], l[2], l[3]);
     t.m = make_uint4(m[0], m[1], m[2], m[3]);
     t.h = make_uint4(h[0], h[1], h[2], h[3]);
-    four_points<K, CLS, TILED>(L, tile, t, first + j0, nv, natom);
+    t.c = make_uint4(c[0], c[1], c[2], c[3]);
+    four_points<K, CLS, TILED, ACC>(L, tile, t, first + j0, nv, natom);
   }
 }
 
@@ -582,16 +646,16 @@ __global__ void __launch_bounds__(256) k_clear_views(ClearViewsArgs a) {
 }
 
 // ------------------------------------------------------------------ render
-template <int K, bool TILED>
+template <int K, bool TILED, bool ACC = false>
 __device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const Streams& a, uint64_t* tile,
                                                 uint32_t first, uint32_t count, uint32_t wave, uint32_t lane,
                                                 uint32_t& natom) {
   if (cls == CLS_INSIDE)
-    raster_points<K, CLS_INSIDE, TILED>(L, a, tile, first, count, wave, lane, natom);
+    raster_points<K, CLS_INSIDE, TILED, ACC>(L, a, tile, first, count, wave, lane, natom);
   else if (cls == CLS_PARTIAL)
-    raster_points<K, CLS_PARTIAL, TILED>(L, a, tile, first, count, wave, lane, natom);
+    raster_points<K, CLS_PARTIAL, TILED, ACC>(L, a, tile, first, count, wave, lane, natom);
   else if constexpr (!TILED)
-    raster_points<K, CLS_SLOW, false>(L, a, tile, first, count, wave, lane, natom);
+    raster_points<K, CLS_SLOW, false, ACC>(L, a, tile, first, count, wave, lane, natom);
 }
 
 // One live batch of one view by the whole workgroup: its points into the LDS
@@ -681,7 +745,7 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
   uint32_t* const qc = &a.hdr->queue[q][0];
   if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
   const uint32_t nlive = a.hdr->live_count;
-  const Streams st = {a.low, a.med, a.high};
+  const Streams st = {a.low, a.med, a.high, nullptr};
   __syncthreads();
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
@@ -708,7 +772,7 @@ __global__ void __launch_bounds__(THREADS) k_render_views(RenderViewsArgs a) {
   uint32_t* const qc = &a.hdr->queue[q][0];
   if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
   const uint32_t nruns = a.hdr->live_count;
-  const Streams st = {a.low, a.med, a.high};
+  const Streams st = {a.low, a.med, a.high, nullptr};
   __syncthreads();
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
@@ -729,6 +793,118 @@ __global__ void __launch_bounds__(THREADS) k_render_views(RenderViewsArgs a) {
     i = uni(s_next);
   }
   add_atomics<CNT>(a.stats, natom, lane);
+}
+
+// ------------------------------------------------------------------ shading
+// High-quality shading (Sec. 3.6), second pass over the live batches of the
+// frame's render: every drawn point within the depth window of its pixel
+// adds its colour and a count.  Tiled batches whose rectangle fits HQS_TILE
+// pixels stage the thresholds of the rectangle in LDS, add into LDS sums and
+// flush each covered pixel with two global additions; the others read the
+// visibility buffer and add globally per point.  Integer sums: the result
+// does not depend on the order of the additions.
+constexpr uint32_t HQS_TILE = 1536;  // 6 KiB of thresholds + 24 KiB of sums
+
+__global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
+  __shared__ float thr[HQS_TILE];
+  __shared__ uint64_t sums[2 * HQS_TILE];
+  __shared__ uint32_t s_next;
+  const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
+  const uint32_t q = blockIdx.x % RENDER_QUEUES;
+  uint32_t* const qc = &a.hdr->queue[q][0];
+  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+  const uint32_t nlive = a.hdr->live_count;
+  const Streams st = {a.low, a.med, a.high, a.colors};
+  __syncthreads();
+  uint32_t i = uni(s_next);
+  uint32_t natom = 0;
+  while (i < nlive) {
+    uint32_t grab = 0;
+    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    const LiveBatch& rec = a.live[i];
+    Loop L;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) L.P[r][j] = rec.P[r][j];
+      L.t[r] = rec.t[r];
+    }
+    L.W = a.W;
+    L.H = a.H;
+    L.vb = a.vb;
+    L.window = a.window;
+    L.acc = a.accum;
+    L.thr = thr;
+    const uint32_t mode = rec.mode, rxy = rec.rect_xy, rwh = rec.rect_wh;
+    const uint32_t first = rec.first, count = rec.count;
+    const uint32_t x0 = rxy & 0xFFFFu, y0 = rxy >> 16;
+    L.tw = rwh & 0xFFFFu;
+    L.th = rwh >> 16;
+    L.tw8 = L.tw * 8u;
+    const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
+    const uint32_t n = L.tw * L.th;
+    const bool tiled = ((mode >> 16) & 1u) && n <= HQS_TILE;
+    L.cx = in_vgpr(uni(0x4B000000u + (tiled ? x0 : 0u)));
+    L.cy = in_vgpr(uni(0x4B000000u + (tiled ? y0 : 0u)));
+    if (tiled) {
+      for (uint32_t e = tid; e < n; e += THREADS) {
+        const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
+        const uint64_t key = a.vb[(y0 + ly) * a.W + (x0 + lx)];
+        thr[e] = __uint_as_float((uint32_t)(key >> 32)) * a.window;
+        sums[2 * e] = 0;
+        sums[2 * e + 1] = 0;
+      }
+      __syncthreads();
+      if (k == 10) raster_by_class<10, true, true>(cls, L, st, sums, first, count, wave, lane, natom);
+      else if (k == 20) raster_by_class<20, true, true>(cls, L, st, sums, first, count, wave, lane, natom);
+      else raster_by_class<30, true, true>(cls, L, st, sums, first, count, wave, lane, natom);
+    } else {
+      if (k == 10) raster_by_class<10, false, true>(cls, L, st, sums, first, count, wave, lane, natom);
+      else if (k == 20) raster_by_class<20, false, true>(cls, L, st, sums, first, count, wave, lane, natom);
+      else raster_by_class<30, false, true>(cls, L, st, sums, first, count, wave, lane, natom);
+    }
+    __syncthreads();  // the batch's sums are complete; s_next has been read
+    if (tid == 0) s_next = grab;
+    if (tiled) {
+      for (uint32_t e = tid; e < n; e += THREADS) {
+        const uint64_t bn = sums[2 * e + 1];
+        if (bn >> 32) {
+          const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
+          uint64_t* const g = a.accum + 2 * (uint64_t)((y0 + ly) * a.W + (x0 + lx));
+          __hip_atomic_fetch_add(g, sums[2 * e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(g + 1, bn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    __syncthreads();  // tile free for the next batch; s_next visible
+    i = uni(s_next);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_reset_queues(FrameHeader* hdr) {
+  if (threadIdx.x < RENDER_QUEUES) hdr->queue[threadIdx.x][0] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_zero64(uint64_t* p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+// The average of the sums: each channel (sum + n / 2) / n, alpha 255; the
+// clear colour where no point joined.
+__global__ void __launch_bounds__(256) k_resolve_hqs(const uint64_t* __restrict__ acc, uint64_t npix,
+                                                     uint32_t clear_rgba, uint32_t* __restrict__ fb) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const uint64_t rg = acc[2 * p], bn = acc[2 * p + 1];
+  const uint64_t n = bn >> 32;
+  if (n == 0) {
+    fb[p] = clear_rgba;
+    return;
+  }
+  const uint64_t r = ((rg & 0xFFFFFFFFull) + n / 2) / n, g = ((rg >> 32) + n / 2) / n;
+  const uint64_t b = ((bn & 0xFFFFFFFFull) + n / 2) / n;
+  fb[p] = (uint32_t)r | ((uint32_t)g << 8) | ((uint32_t)b << 16) | (255u << 24);
 }
 
 // ------------------------------------------------------------------ resolve
@@ -832,6 +1008,35 @@ hipError_t launch_render_views(const RenderViewsArgs& a, uint64_t max_runs, int 
     hipLaunchKernelGGL(k_render_views<true>, dim3(blocks), dim3(THREADS), 0, s, a);
   else
     hipLaunchKernelGGL(k_render_views<false>, dim3(blocks), dim3(THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+uint32_t accum_grid(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_accum, THREADS, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  return (uint32_t)(per_cu * cus);
+}
+
+hipError_t launch_accumulate(const RenderArgs& a, hipStream_t s) {
+  const uint64_t n = 2ull * a.W * a.H;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero64, dim3((uint32_t)blocks), dim3(256), 0, s, a.accum, n);
+  if (a.nb == 0) return hipGetLastError();
+  // the shading pass walks the render's live list with fresh work-queue counters
+  hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, s, a.hdr);
+  const uint32_t blocks_r = a.grid < a.nb ? a.grid : a.nb;
+  hipLaunchKernelGGL(k_accum, dim3(blocks_r), dim3(THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_hqs(const uint64_t* accum, uint64_t npix, uint32_t clear_rgba, uint32_t* fb,
+                              hipStream_t s) {
+  const uint64_t blocks = (npix + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resolve_hqs, dim3((uint32_t)blocks), dim3(256), 0, s, accum, npix, clear_rgba, fb);
   return hipGetLastError();
 }
 

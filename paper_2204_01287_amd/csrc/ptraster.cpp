@@ -20,6 +20,7 @@ struct pr_ctx {
   ptr::DevBlock* dev;  // counters and flags (device memory)
   uint32_t render_grid;        // persistent render workgroups that fit on the device at once
   uint32_t render_views_grid;  // the same for the multi-view render kernel
+  uint32_t accum_grid;         // and for the shading pass
 };
 
 struct pr_cloud {
@@ -138,6 +139,7 @@ pr_status pr_create(int device, void* hip_stream, pr_ctx** out) {
   c->dev = nullptr;
   c->render_grid = ptr::render_grid(device);
   c->render_views_grid = ptr::render_views_grid(device);
+  c->accum_grid = ptr::accum_grid(device);
   e = hipMalloc(reinterpret_cast<void**>(&c->dev), 4096);
   if (e != hipSuccess) {
     delete c;
@@ -261,31 +263,40 @@ pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, in
   return PR_OK;
 }
 
-pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16], uint32_t w,
-                    uint32_t h, const pr_render_opts* opts, uint64_t* visbuf) {
-  if (!ctx || !cloud || !view || !proj || !visbuf) return fail(PR_EINVAL, "pr_render: NULL argument");
-  if (cloud->ctx->device != ctx->device) return fail(PR_EINVAL, "pr_render: cloud lives on another device");
+namespace {
+
+// Argument checks shared by pr_render and pr_render_hqs.
+pr_status check_render(const char* fn, pr_ctx* ctx, const pr_cloud* cloud, const float* view, const float* proj,
+                       uint32_t w, uint32_t h, const pr_render_opts* opts, uint64_t* visbuf, pr_render_opts* o) {
+  if (!ctx || !cloud || !view || !proj || !visbuf) return fail(PR_EINVAL, "%s: NULL argument", fn);
+  if (cloud->ctx->device != ctx->device) return fail(PR_EINVAL, "%s: cloud lives on another device", fn);
+  if (!cloud->built) return fail(PR_ESTATE, "%s: cloud is not built (call pr_build_batches)", fn);
   if (cloud->load_dropped)
-    return fail(PR_ESTATE, "pr_render: the cloud's scratch was released (pr_cloud_drop_load_buffers); use pr_render_views");
-  if (!cloud->built) return fail(PR_ESTATE, "pr_render: cloud is not built (call pr_build_batches)");
+    return fail(PR_ESTATE, "%s: the cloud's scratch was released (pr_cloud_drop_load_buffers); use pr_render_views",
+                fn);
   if (pr_status s = check_dims(w, h)) return s;
-  if (reinterpret_cast<uintptr_t>(visbuf) & 15u) return fail(PR_EINVAL, "pr_render: visbuf must be 16-byte aligned");
-  pr_render_opts o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0};
-  if (opts) o = *opts;
-  if (o.precision != PR_ADAPTIVE && o.precision != PR_FORCE10 && o.precision != PR_FORCE20 &&
-      o.precision != PR_FORCE30)
-    return fail(PR_EINVAL, "pr_render: precision %d is not 0, 10, 20 or 30", o.precision);
-  if (std::isnan(o.t10) || std::isnan(o.t20)) return fail(PR_EINVAL, "pr_render: NaN threshold");
+  if (reinterpret_cast<uintptr_t>(visbuf) & 15u) return fail(PR_EINVAL, "%s: visbuf must be 16-byte aligned", fn);
+  *o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0};
+  if (opts) *o = *opts;
+  if (o->precision != PR_ADAPTIVE && o->precision != PR_FORCE10 && o->precision != PR_FORCE20 &&
+      o->precision != PR_FORCE30)
+    return fail(PR_EINVAL, "%s: precision %d is not 0, 10, 20 or 30", fn, o->precision);
+  if (std::isnan(o->t10) || std::isnan(o->t20)) return fail(PR_EINVAL, "%s: NaN threshold", fn);
   for (int i = 0; i < 16; ++i)
-    if (!std::isfinite(view[i]) || !std::isfinite(proj[i])) return fail(PR_ENONFINITE, "pr_render: non-finite matrix");
-  if (pr_status s = set_device(ctx)) return s;
+    if (!std::isfinite(view[i]) || !std::isfinite(proj[i])) return fail(PR_ENONFINITE, "%s: non-finite matrix", fn);
+  return set_device(ctx);
+}
+
+// Clear (or, when accumulating, only reset the frame's work queue and
+// counters), classify and render one view; a receives the frame's arguments.
+pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16], uint32_t w,
+                       uint32_t h, const pr_render_opts& o, uint64_t* visbuf, ptr::RenderArgs& a) {
   const uint64_t npix = (uint64_t)w * h;
   ptr::FrameHeader* hdr =
       reinterpret_cast<ptr::FrameHeader*>(static_cast<uint8_t*>(cloud->bufs.scratch) + ptr::small_scratch_bytes());
-  // clear (or, when accumulating, only reset the frame's work queue and counters)
   HIP_TRY(ptr::launch_clear(visbuf, o.accumulate ? 0 : npix, ctx->dev, hdr, o.counters ? 1 : 0, ctx->stream),
           "clear");
-  ptr::RenderArgs a;
+  std::memset(&a, 0, sizeof a);
   a.low = static_cast<const uint32_t*>(cloud->bufs.low);
   a.med = static_cast<const uint32_t*>(cloud->bufs.med);
   a.high = static_cast<const uint32_t*>(cloud->bufs.high);
@@ -305,6 +316,37 @@ pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], co
   a.t10 = o.t10;
   a.t20 = o.t20;
   HIP_TRY(ptr::launch_render(a, ctx->stream), "render");
+  return PR_OK;
+}
+
+}  // namespace
+
+pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16], uint32_t w,
+                    uint32_t h, const pr_render_opts* opts, uint64_t* visbuf) {
+  pr_render_opts o;
+  if (pr_status s = check_render("pr_render", ctx, cloud, view, proj, w, h, opts, visbuf, &o)) return s;
+  ptr::RenderArgs a;
+  return render_frame(ctx, cloud, view, proj, w, h, o, visbuf, a);
+}
+
+pr_status pr_render_hqs(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16], uint32_t w,
+                        uint32_t h, const pr_render_opts* opts, float window, uint64_t* visbuf, uint64_t* accum,
+                        uint32_t clear_rgba, uint32_t* rgba_out) {
+  pr_render_opts o;
+  if (pr_status s = check_render("pr_render_hqs", ctx, cloud, view, proj, w, h, opts, visbuf, &o)) return s;
+  if (!accum || !rgba_out) return fail(PR_EINVAL, "pr_render_hqs: NULL argument");
+  if ((reinterpret_cast<uintptr_t>(accum) & 15u) || (reinterpret_cast<uintptr_t>(rgba_out) & 15u))
+    return fail(PR_EINVAL, "pr_render_hqs: accum and rgba_out must be 16-byte aligned");
+  if (o.accumulate) return fail(PR_EINVAL, "pr_render_hqs: accumulate is not supported (the depth pass is a frame)");
+  if (!(window >= 1.0f) || !std::isfinite(window)) return fail(PR_EINVAL, "pr_render_hqs: window must be finite and >= 1");
+  ptr::RenderArgs a;
+  if (pr_status s = render_frame(ctx, cloud, view, proj, w, h, o, visbuf, a)) return s;
+  a.colors = static_cast<const uint32_t*>(cloud->bufs.colors);
+  a.accum = accum;
+  a.window = window;
+  a.grid = ctx->accum_grid;
+  HIP_TRY(ptr::launch_accumulate(a, ctx->stream), "shading pass");
+  HIP_TRY(ptr::launch_resolve_hqs(accum, (uint64_t)w * h, clear_rgba, rgba_out, ctx->stream), "shading resolve");
   return PR_OK;
 }
 

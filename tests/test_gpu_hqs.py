@@ -1,0 +1,135 @@
+"""High-quality shading (pr_render_hqs, Sec. 3.6) against the oracle, bit for bit.
+
+The visibility buffer, the two 64-bit sum words per pixel and the averaged framebuffer must equal the oracle's
+or_render / or_accumulate / or_resolve_hqs on the same inputs: the hand-derived worked example, the 1M-point
+primitives cloud at several depth windows and precision modes, and a 2M-point Morton terrain (orbit view and
+stereo pair); plus the argument checks.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import MODES, assert_vb_equal, gpu_build, say
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2204_01287_amd as pr
+
+    assert torch.cuda.is_available()
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_hqs(ctx, dc, cam_view, cam_proj, w, h, window, clear=0, **opt):
+    import torch
+    import paper_2204_01287_amd as pr
+
+    vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
+    acc = torch.empty(2 * w * h, dtype=torch.int64, device="cuda")
+    fb = torch.empty(w * h, dtype=torch.int32, device="cuda")
+    say(f"hqs n={dc.n} {w}x{h} window={window} opts={opt}")
+    pr.pr_render_hqs(ctx.handle, dc.handle, cam_view, cam_proj, w, h, pr.RenderOpts.make(**opt), window, vb, acc,
+                     clear, fb)
+    pr.pr_sync(ctx.handle)
+    return (vb.cpu().numpy().view(np.uint64), acc.cpu().numpy().view(np.uint64), fb.cpu().numpy().view(np.uint32))
+
+
+def check(ctx, dc, B, cam_view, cam_proj, w, h, window, clear=0xFF000000, mode="adaptive"):
+    opt = dict(MODES[mode])
+    vb, acc, fb = gpu_hqs(ctx, dc, cam_view, cam_proj, w, h, window, clear, **opt)
+    o = oracle.opts(precision=opt.get("precision", 0), cull=opt.get("cull", 1))
+    ref, _ = oracle.render(B, cam_view, cam_proj, w, h, o)
+    assert_vb_equal(vb, ref, w)
+    racc = oracle.accumulate(B, cam_view, cam_proj, w, h, ref, window=window, o=o)
+    if not np.array_equal(acc, racc):
+        bad = np.nonzero(acc != racc)[0]
+        raise AssertionError(f"{len(bad)} sum words differ, first at pixel {bad[0] // 2}: gpu {int(acc[bad[0]]):#x} "
+                             f"oracle {int(racc[bad[0]]):#x}")
+    assert np.array_equal(fb, oracle.resolve_hqs(racc, clear))
+    n = acc[1::2] >> np.uint64(32)
+    assert np.array_equal(n > 0, ref != oracle.EMPTY)  # the closest point always joins
+    return acc
+
+
+def test_worked_example(ctx):
+    with open(GOLD) as f:
+        g = json.load(f)
+    xyz = np.array(g["points"], np.float32)
+    cols = np.array([int(c, 16) for c in g["colors"]], np.uint32)
+    dc = gpu_build(ctx, xyz, cols, g["batch_size"], False)
+    view, proj = np.array(g["view"], np.float32), np.array(g["proj"], np.float32)
+    for window, want in g["hqs"].items():
+        vb, acc, fb = gpu_hqs(ctx, dc, view, proj, g["width"], g["height"], float(window))
+        for p, (a0, a1) in want["acc"].items():
+            assert (int(acc[2 * int(p)]), int(acc[2 * int(p) + 1])) == (a0, a1)
+        assert int(np.count_nonzero(acc)) == 2 * len(want["acc"])
+        for p, c in want["fb"].items():
+            assert int(fb[int(p)]) == int(c, 16)
+
+
+@pytest.fixture(scope="module")
+def c1(ctx):
+    xyz, rgba = synth.primitives(synth.C1_SEED, 1_000_000)
+    return gpu_build(ctx, xyz, rgba, 10240, False), oracle.build_cloud(xyz, rgba, 10240, morton=False)
+
+
+@pytest.mark.parametrize("window,mode", [(1.0, "adaptive"), (1.01, "adaptive"), (1.01, "force30"),
+                                         (1.01, "adaptive_nocull"), (1.5, "force10"), (4.0, "adaptive")])
+def test_c1(ctx, c1, window, mode):
+    dc, B = c1
+    cam = synth.c1_camera()
+    check(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, window, mode=mode)
+
+
+def test_c1_random_cameras(ctx, c1):
+    dc, B = c1
+    rng = np.random.default_rng(5)
+    for i in range(4):
+        cam = synth.random_camera(rng, 256, 192, inside=(i == 0), box=((0, 0, 0), (100, 100, 100)))
+        check(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, 1.02)
+
+
+@pytest.fixture(scope="module")
+def terrain(ctx):
+    xyz, rgba = synth.terrain(synth.C2_SEED, 2_000_000, order=1)
+    return gpu_build(ctx, xyz, rgba, 10240, True), oracle.build_cloud(xyz, rgba, 10240, morton=True)
+
+
+def test_terrain_orbit_and_stereo(ctx, terrain):
+    dc, B = terrain
+    cams = [synth.orbit_camera(9, width=960, height=540)] + synth.stereo_cameras(synth.C2_SEED, 504, 560)
+    for cam in cams:
+        acc = check(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, 1.01)
+        assert int((acc[1::2] >> np.uint64(32)).max()) > 1  # pixels blend several points
+
+
+def test_argument_checks(ctx, c1):
+    import torch
+    import paper_2204_01287_amd as pr
+
+    dc, _ = c1
+    cam = synth.c1_camera()
+    w, h = cam.width, cam.height
+    vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
+    acc = torch.empty(2 * w * h + 2, dtype=torch.int64, device="cuda")
+    fb = torch.empty(w * h, dtype=torch.int32, device="cuda")
+    for window in (0.99, float("nan"), float("inf")):
+        with pytest.raises(pr.PrError, match="PR_EINVAL"):
+            pr.pr_render_hqs(ctx.handle, dc.handle, cam.view, cam.proj, w, h, None, window, vb, acc, 0, fb)
+    with pytest.raises(pr.PrError, match="PR_EINVAL"):
+        pr.pr_render_hqs(ctx.handle, dc.handle, cam.view, cam.proj, w, h, pr.RenderOpts.make(accumulate=1), 1.01,
+                         vb, acc, 0, fb)
+    with pytest.raises(pr.PrError, match="PR_EINVAL"):
+        pr.pr_render_hqs(ctx.handle, dc.handle, cam.view, cam.proj, w, h, None, 1.01, vb, acc.data_ptr() + 8, 0, fb)
+    pr.pr_sync(ctx.handle)

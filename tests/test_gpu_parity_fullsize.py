@@ -300,3 +300,33 @@ def test_c3_stereo_one_launch(ctx, c3):
         tot = s if tot is None else {k: (tot[k] + s[k] if not isinstance(s[k], list) else
                                          [a + b for a, b in zip(tot[k], s[k])]) for k in s}
     oracle_stats_match(st, tot)
+
+
+def test_c3_hqs_eye0(ctx, c3):
+    """High-quality shading of eye 0: sums and averaged framebuffer equal the oracle's (threads over interleaved
+    batch sets, private sums added modulo 2^64, exact)."""
+    import torch
+    import paper_2204_01287_amd as pr
+
+    cam = c3.wl["cams"][0]
+    w, h = cam.width, cam.height
+    vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
+    acc = torch.empty(2 * w * h, dtype=torch.int64, device="cuda")
+    fb = torch.empty(w * h, dtype=torch.int32, device="cuda")
+    say("C3: high-quality shading of eye 0")
+    pr.pr_render_hqs(ctx.handle, c3.cloud["handle"], cam.view, cam.proj, w, h, None, 1.01, vb, acc, CLEAR, fb)
+    pr.pr_sync(ctx.handle)
+    ref, _ = _oracle_frame(c3.built, cam, c3.nb)
+    assert_vb_equal(vb.cpu().numpy().view(np.uint64), ref, w)
+    groups = [np.arange(g, c3.nb, 4 * RENDER_WORKERS, dtype=np.uint64) for g in range(4 * RENDER_WORKERS)]
+
+    def job(ids):
+        return oracle.accumulate(c3.built, cam.view, cam.proj, w, h, ref, window=1.01, batch_ids=ids,
+                                 colors=c3.colors)
+
+    racc = np.zeros(2 * w * h, np.uint64)
+    with ThreadPoolExecutor(RENDER_WORKERS) as ex:
+        for part in ex.map(job, groups):
+            racc += part
+    assert np.array_equal(acc.cpu().numpy().view(np.uint64), racc)
+    assert np.array_equal(fb.cpu().numpy().view(np.uint32), oracle.resolve_hqs(racc, CLEAR))
