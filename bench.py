@@ -232,6 +232,39 @@ def multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, plain
     return res
 
 
+def hqs_leg(pr, ctx, cloud, cams, processed, steps, warmup, window=1.01):
+    """The stereo step with high-quality shading (Sec. 3.6) instead of the plain resolve: per eye, the render,
+    the shading pass (colour sums within the depth window) and the averaging resolve."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    bufs = [(torch.empty(c.width * c.height, dtype=torch.int64, device="cuda"),
+             torch.empty(2 * c.width * c.height, dtype=torch.int64, device="cuda"),
+             torch.empty(c.width * c.height, dtype=torch.int32, device="cuda")) for c in cams]
+
+    def step():
+        for c, (vb, acc, fb) in zip(cams, bufs):
+            pr.pr_render_hqs(ctx.handle, cloud["handle"], c.view, c.proj, c.width, c.height, None, window, vb, acc,
+                             0xFF000000, fb)
+
+    for _ in range(warmup):
+        step()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    pr.pr_sync(ctx.handle)
+    t = [a.elapsed_time(b) for a, b in ev]
+    res = {"window": window, "ms_per_step": round(float(np.mean(t)), 4),
+           "gpts": round(processed / (float(np.mean(t)) * 1e-3) / 1e9, 3)}
+    log(f"high-quality shading: {res}")
+    return res
+
+
 def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
     """Served workload: 8 resident terrain clouds (3.41e9 points), a seeded Poisson request stream with random
     cameras and image sizes 640x480 / 1920x1080 / 3840x2160, admission by visibility + framebuffer bytes.
@@ -419,6 +452,7 @@ def main():
     }
     out["multiview"] = multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, ms_per_step,
                                             args.steps, args.warmup)
+    out["hqs"] = hqs_leg(pr, ctx, cloud, cams, processed, args.steps, args.warmup)
     pr.pr_cloud_free(cloud["handle"])
     cloud["mem"].clear()
     torch.cuda.empty_cache()
