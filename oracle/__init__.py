@@ -28,7 +28,7 @@ DECISION_DTYPE = np.dtype([("culled", "<i4"), ("level", "<i4"), ("P", "<f4", (3,
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cull", ctypes.c_int), ("t10", ctypes.c_float),
-                ("t20", ctypes.c_float)]
+                ("t20", ctypes.c_float), ("lod_px", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -72,11 +72,12 @@ def _lib_():
         L.or_build.argtypes = [P, P, U64, U32, I, P, P, P, P, P, P, P]
         L.or_build.restype = I
         L.or_frame_matrix.argtypes = [P, P, U32, U32, P]
-        L.or_decide_all.argtypes = [P, U64, P, P, U32, U32, ctypes.POINTER(Opts), P]
-        L.or_render.argtypes = [P, U64, P, U64, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts), P,
+        L.or_decide_all.argtypes = [P, P, U64, P, P, U32, U32, ctypes.POINTER(Opts), P]
+        L.or_render.argtypes = [P, P, U64, P, U64, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts), P,
                                 ctypes.POINTER(Stats)]
+        L.or_make_batches_spans.argtypes = [P, P, U64, P]
         L.or_resolve.argtypes = [P, U64, P, U64, U32, P]
-        L.or_accumulate.argtypes = [P, U64, P, U64, P, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts),
+        L.or_accumulate.argtypes = [P, P, U64, P, U64, P, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts),
                                     ctypes.c_float, P, P]
         L.or_resolve_hqs.argtypes = [P, U64, U32, P]
         _lib = L
@@ -92,8 +93,8 @@ def _c(a, dtype):
     return a
 
 
-def opts(precision: int = 0, cull: int = 1, t10: float = 500.0, t20: float = 512000.0) -> Opts:
-    return Opts(precision, cull, t10, t20)
+def opts(precision: int = 0, cull: int = 1, t10: float = 500.0, t20: float = 512000.0, lod_px: float = 0.0) -> Opts:
+    return Opts(precision, cull, t10, t20, lod_px)
 
 
 def validate(xyz) -> int:
@@ -161,6 +162,7 @@ class Built:
         self.low = np.empty(n, np.uint32)
         self.med = np.empty(n, np.uint32)
         self.high = np.empty(n, np.uint32)
+        self.nodes = None  # LOD layouts: float64 (nb, 5) = cube origin x, y, z, edge, level
 
 
 def build_cloud(xyz, rgba, S: int = 10240, morton: bool = False) -> Built:
@@ -175,6 +177,29 @@ def build_cloud(xyz, rgba, S: int = 10240, morton: bool = False) -> Built:
     return B
 
 
+def build_cloud_spans(xyz, rgba, spans, nodes=None) -> Built:
+    """Variable-size batches given as spans (first, count) over xyz / rgba in render order (Sec. 3.5); slots
+    outside every span are padding.  nodes: optional LOD node per batch (cube origin x, y, z, edge, level)."""
+    xyz = _c(xyz, np.float32)
+    rgba = _c(rgba, np.uint32)
+    spans = _c(spans, np.uint32)
+    n, nb = xyz.shape[0], spans.shape[0]
+    if nb and (np.any(spans[:, 0] % 4) or int((spans[:, 0].astype(np.uint64) + spans[:, 1]).max()) > n):
+        raise ValueError("spans must start at multiples of 4 and lie inside the cloud")
+    B = Built(n, max(n, 1))
+    B.xyz[:] = xyz
+    B.colors[:] = rgba
+    B.perm[:] = np.arange(n, dtype=np.uint32)
+    B.batches = np.empty(nb, BATCH_DTYPE)
+    _lib_().or_make_batches_spans(_p(xyz), _p(spans), nb, _p(B.batches))
+    B.low[:] = 0
+    B.med[:] = 0
+    B.high[:] = 0
+    _lib_().or_quantize(_p(xyz), _p(B.batches), nb, _p(B.low), _p(B.med), _p(B.high))
+    B.nodes = None if nodes is None else _c(nodes, np.float64)
+    return B
+
+
 def frame_matrix(view, proj, w: int, h: int):
     view = _c(view, np.float32)
     proj = _c(proj, np.float32)
@@ -183,12 +208,14 @@ def frame_matrix(view, proj, w: int, h: int):
     return Pm
 
 
-def decide_all(batches, view, proj, w: int, h: int, o: Opts | None = None):
+def decide_all(batches, view, proj, w: int, h: int, o: Opts | None = None, nodes=None):
     o = o or opts()
     view = _c(view, np.float32)
     proj = _c(proj, np.float32)
+    nd = None if nodes is None else _c(nodes, np.float64)
     out = np.empty(batches.shape[0], DECISION_DTYPE)
-    _lib_().or_decide_all(_p(batches), batches.shape[0], _p(view), _p(proj), w, h, ctypes.byref(o), _p(out))
+    _lib_().or_decide_all(_p(batches), _p(nd), batches.shape[0], _p(view), _p(proj), w, h, ctypes.byref(o),
+                          _p(out))
     return out
 
 
@@ -201,7 +228,8 @@ def render(built: Built, view, proj, w: int, h: int, o: Opts | None = None, batc
         vb = np.full(w * h, EMPTY, np.uint64)
     ids = None if batch_ids is None else _c(batch_ids, np.uint64)
     st = Stats()
-    _lib_().or_render(_p(built.batches), built.batches.shape[0], _p(ids), 0 if ids is None else ids.shape[0],
+    nd = getattr(built, "nodes", None)
+    _lib_().or_render(_p(built.batches), _p(nd), built.batches.shape[0], _p(ids), 0 if ids is None else ids.shape[0],
                       _p(built.low), _p(built.med), _p(built.high), _p(view), _p(proj), w, h,
                       ctypes.byref(o), _p(vb), ctypes.byref(st))
     return vb, st.as_dict()
@@ -226,7 +254,8 @@ def accumulate(built: Built, view, proj, w: int, h: int, vb, window: float = 1.0
     cols = _c(built.colors if colors is None else colors, np.uint32)
     acc = np.zeros(2 * w * h, np.uint64)
     ids = None if batch_ids is None else _c(batch_ids, np.uint64)
-    _lib_().or_accumulate(_p(built.batches), built.batches.shape[0], _p(ids), 0 if ids is None else ids.shape[0],
+    nd = getattr(built, "nodes", None)
+    _lib_().or_accumulate(_p(built.batches), _p(nd), built.batches.shape[0], _p(ids), 0 if ids is None else ids.shape[0],
                           _p(built.low), _p(built.med), _p(built.high), _p(cols), _p(view), _p(proj), w, h,
                           ctypes.byref(o), float(np.float32(window)), _p(vb), _p(acc))
     return acc

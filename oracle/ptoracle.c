@@ -48,6 +48,7 @@ typedef struct {
   int precision; /* 0 adaptive, 10/20/30 forced */
   int cull;      /* 1 = batch frustum culling */
   float t10, t20;
+  float lod_px; /* > 0: LOD culling of nodes below this projected size (Sec. 3.5) */
 } or_opts;
 
 typedef struct {
@@ -164,24 +165,36 @@ int or_morton_order(const uint64_t* codes, uint64_t n, uint32_t* perm) {
  * order of f32_less. */
 uint64_t or_batch_count(uint64_t n, uint32_t S) { return (n + S - 1) / S; }
 
+/* The record of the batch of points [lo, hi): first, count and the fp32
+ * bounding box (totalOrder min/max). */
+static void or_batch_of(const float* xyz, uint64_t lo, uint64_t hi, or_batch* B) {
+  B->first = (uint32_t)lo;
+  B->count = (uint32_t)(hi - lo);
+  for (int a = 0; a < 3; ++a) {
+    B->min[a] = INFINITY;
+    B->max[a] = -INFINITY;
+  }
+  for (uint64_t i = lo; i < hi; ++i)
+    for (int a = 0; a < 3; ++a) {
+      float v = xyz[3 * i + a];
+      if (f32_less(v, B->min[a])) B->min[a] = v;
+      if (f32_less(B->max[a], v)) B->max[a] = v;
+    }
+}
+
 void or_make_batches(const float* xyz, uint64_t n, uint32_t S, or_batch* out) {
   uint64_t nb = or_batch_count(n, S);
   for (uint64_t b = 0; b < nb; ++b) {
     uint64_t lo = b * S, hi = lo + S < n ? lo + S : n;
-    or_batch* B = &out[b];
-    B->first = (uint32_t)lo;
-    B->count = (uint32_t)(hi - lo);
-    for (int a = 0; a < 3; ++a) {
-      B->min[a] = INFINITY;
-      B->max[a] = -INFINITY;
-    }
-    for (uint64_t i = lo; i < hi; ++i)
-      for (int a = 0; a < 3; ++a) {
-        float v = xyz[3 * i + a];
-        if (f32_less(v, B->min[a])) B->min[a] = v;
-        if (f32_less(B->max[a], v)) B->max[a] = v;
-      }
+    or_batch_of(xyz, lo, hi, &out[b]);
   }
+}
+
+/* Variable-size batches (Sec. 3.5: each batch stores its first point and its
+ * number of points): spans[2b] = first, spans[2b + 1] = count. */
+void or_make_batches_spans(const float* xyz, const uint32_t* spans, uint64_t nb, or_batch* out) {
+  for (uint64_t b = 0; b < nb; ++b)
+    or_batch_of(xyz, spans[2 * b], (uint64_t)spans[2 * b] + spans[2 * b + 1], &out[b]);
 }
 
 /* ---------------------------------------------------------------- O4 */
@@ -287,7 +300,32 @@ void or_frame_matrix(const float view[16], const float proj[16], uint32_t w, uin
  *  fold (lower-corner decode: unknown low bits are zero, so a point decodes
  *      to min + F size 2^-k):  P[r][j] = fp32(Pm[r][j] (size_j 2^-k)),
  *      t[r] = fp32(((Pm[r][0] min_x + Pm[r][1] min_y) + Pm[r][2] min_z) + Pm[r][3]). */
-void or_decide(const double Pm[3][4], const or_batch* B, uint32_t w, uint32_t h,
+/* Projected extent of the box [lo, hi] (8 corners, binary64, left-to-right
+ * sums): +inf if a corner has hw <= 0, else the larger side of the screen
+ * box of the projected corners. */
+static double proj_extent(const double Pm[3][4], const double lo[3], const double hi[3]) {
+  double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+  for (int c = 0; c < 8; ++c) {
+    double cx = (c & 1) ? hi[0] : lo[0], cy = (c & 2) ? hi[1] : lo[1], cz = (c & 4) ? hi[2] : lo[2];
+    double hx = ((Pm[0][0] * cx + Pm[0][1] * cy) + Pm[0][2] * cz) + Pm[0][3];
+    double hy = ((Pm[1][0] * cx + Pm[1][1] * cy) + Pm[1][2] * cz) + Pm[1][3];
+    double hw = ((Pm[2][0] * cx + Pm[2][1] * cy) + Pm[2][2] * cz) + Pm[2][3];
+    if (!(hw > 0.0)) return INFINITY;
+    double u = hx / hw, v = hy / hw;
+    if (u < umin) umin = u;
+    if (u > umax) umax = u;
+    if (v < vmin) vmin = v;
+    if (v > vmax) vmax = v;
+  }
+  double ex = umax - umin, ey = vmax - vmin;
+  return ex > ey ? ex : ey;
+}
+
+/* node: NULL, or the batch's octree node (cube origin x, y, z, edge, level).
+ * LOD (Sec. 3.5): with o->lod_px > 0, a batch of a node below the root
+ * (level >= 1) is culled iff the projected extent of the node's cube is
+ * below lod_px; the root is never culled this way. */
+void or_decide(const double Pm[3][4], const or_batch* B, const double* node, uint32_t w, uint32_t h,
                const or_opts* o, or_decision* d) {
   double s[3];
   for (int a = 0; a < 3; ++a) s[a] = (double)B->max[a] - (double)B->min[a];
@@ -314,6 +352,11 @@ void or_decide(const double Pm[3][4], const or_batch* B, uint32_t w, uint32_t h,
     if (!(H[1][c] - Hd * H[2][c] > M[1] + Hd * M[2])) top = 0;
   }
   d->culled = o->cull ? (behind | left | right | bottom | top) : 0;
+  if (!d->culled && o->lod_px > 0.0f && node && node[4] >= 1.0) {
+    double lo[3] = {node[0], node[1], node[2]};
+    double hi[3] = {node[0] + node[3], node[1] + node[3], node[2] + node[3]};
+    if (proj_extent(Pm, lo, hi) < (double)o->lod_px) d->culled = 1;
+  }
 
   int k;
   if (o->precision == 10 || o->precision == 20 || o->precision == 30) {
@@ -395,7 +438,7 @@ static int or_point(const or_decision* d, const uint32_t* low, const uint32_t* m
   return 1;
 }
 
-void or_render(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, uint64_t nids,
+void or_render(const or_batch* batches, const double* nodes, uint64_t nb, const uint64_t* batch_ids, uint64_t nids,
                const uint32_t* low, const uint32_t* med, const uint32_t* high, const float view[16],
                const float proj[16], uint32_t w, uint32_t h, const or_opts* o, uint64_t* vb,
                or_stats* st) {
@@ -407,7 +450,7 @@ void or_render(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, 
     uint64_t b = batch_ids ? batch_ids[it] : it;
     const or_batch* B = &batches[b];
     or_decision d;
-    or_decide(Pm, B, w, h, o, &d);
+    or_decide(Pm, B, nodes ? nodes + 5 * b : NULL, w, h, o, &d);
     if (st) st->batches++;
     if (d.culled) {
       if (st) st->culled++;
@@ -430,11 +473,11 @@ void or_render(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, 
 }
 
 /* Per-batch decisions only (for counters and sampled checks). */
-void or_decide_all(const or_batch* batches, uint64_t nb, const float view[16], const float proj[16],
-                   uint32_t w, uint32_t h, const or_opts* o, or_decision* out) {
+void or_decide_all(const or_batch* batches, const double* nodes, uint64_t nb, const float view[16],
+                   const float proj[16], uint32_t w, uint32_t h, const or_opts* o, or_decision* out) {
   double Pm[3][4];
   or_frame_matrix(view, proj, w, h, Pm);
-  for (uint64_t b = 0; b < nb; ++b) or_decide(Pm, &batches[b], w, h, o, &out[b]);
+  for (uint64_t b = 0; b < nb; ++b) or_decide(Pm, &batches[b], nodes ? nodes + 5 * b : NULL, w, h, o, &out[b]);
 }
 
 /* ---------------------------------------------------------------- O8 */
@@ -462,7 +505,7 @@ void or_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint6
  *     fields: acc[2p] += R + G * 2^32, acc[2p + 1] += B + 2^32 (count), with
  *     R, G, B the low three bytes of the point's colour; additions wrap
  *     modulo 2^64 (exact while a pixel's sums stay below 2^32). */
-void or_accumulate(const or_batch* batches, uint64_t nb, const uint64_t* batch_ids, uint64_t nids,
+void or_accumulate(const or_batch* batches, const double* nodes, uint64_t nb, const uint64_t* batch_ids, uint64_t nids,
                    const uint32_t* low, const uint32_t* med, const uint32_t* high, const uint32_t* colors,
                    const float view[16], const float proj[16], uint32_t w, uint32_t h, const or_opts* o,
                    float window, const uint64_t* vb, uint64_t* acc) {
@@ -470,9 +513,10 @@ void or_accumulate(const or_batch* batches, uint64_t nb, const uint64_t* batch_i
   or_frame_matrix(view, proj, w, h, Pm);
   uint64_t n_iter = batch_ids ? nids : nb;
   for (uint64_t it = 0; it < n_iter; ++it) {
-    const or_batch* B = &batches[batch_ids ? batch_ids[it] : it];
+    uint64_t b = batch_ids ? batch_ids[it] : it;
+    const or_batch* B = &batches[b];
     or_decision d;
-    or_decide(Pm, B, w, h, o, &d);
+    or_decide(Pm, B, nodes ? nodes + 5 * b : NULL, w, h, o, &d);
     if (d.culled) continue;
     for (uint64_t i = B->first; i < (uint64_t)B->first + B->count; ++i) {
       float hw;

@@ -50,6 +50,11 @@ def _load():
         lib.synth_terrain_gather.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64,
                                              ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.synth_terrain_gather.restype = ctypes.c_int
+        lib.synth_lpc_layout.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+        lib.synth_lpc_layout.restype = ctypes.c_int
         lib.synth_terrain_height.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double]
         lib.synth_terrain_height.restype = ctypes.c_double
         _lib = lib
@@ -234,3 +239,37 @@ def request_stream(seed: int, n: int, rate: float, cloud_seeds, sizes=SERVED_SIZ
         w, h = sizes[int(rng.integers(len(sizes)))]
         out.append((float(arrivals[i]), c, served_camera(rng, cloud_seeds[c], w, h)))
     return out
+
+
+# ------------------------------------------------------------ LOD input
+def lpc_depth(n: int, cap: int = 10240) -> int:
+    """Deepest level so that the last level's nodes (3/4 of the points, 4^depth nodes on a surface) hold about cap."""
+    d = 0
+    while d < 15 and 0.75 * n / (4 ** d) > cap:
+        d += 1
+    return d
+
+
+def lpc_layout(seed: int, xyz, rgba, depth: int, cap: int = 10240):
+    """Layered-point-cloud layout (see synth_lpc_layout): (xyz_out, rgba_out, spans uint32 (nb, 2) = first, count,
+    nodes float64 (nb, 5) = cube origin x, y, z, edge, level).  Padding slots between batches are zero."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    rgba = np.ascontiguousarray(rgba, dtype=np.uint32)
+    n = xyz.shape[0]
+    npad, nb = ctypes.c_uint64(), ctypes.c_uint64()
+    cap_b = n // max(1, cap // 4) + 2 * 4 ** min(depth, 10) + 16
+    cap_p = n + 3 * cap_b
+    for _ in range(2):
+        xo = np.zeros((cap_p, 3), np.float32)
+        ro = np.zeros(cap_p, np.uint32)
+        spans = np.zeros((cap_b, 2), np.uint32)
+        nodes = np.zeros((cap_b, 5), np.float64)
+        rc = _load().synth_lpc_layout(seed, xyz.ctypes.data, rgba.ctypes.data, n, depth, cap, xo.ctypes.data,
+                                      ro.ctypes.data, cap_p, spans.ctypes.data, nodes.ctypes.data, cap_b,
+                                      ctypes.byref(npad), ctypes.byref(nb))
+        if rc == 0:
+            return xo[:npad.value].copy(), ro[:npad.value].copy(), spans[:nb.value].copy(), nodes[:nb.value].copy()
+        if rc != -3:
+            raise RuntimeError(f"synth_lpc_layout failed ({rc})")
+        cap_b, cap_p = nb.value, npad.value
+    raise RuntimeError("synth_lpc_layout: capacity")

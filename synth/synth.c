@@ -489,3 +489,148 @@ int synth_terrain(uint64_t seed, uint64_t n, double sigma, int order, float* xyz
   free(J.B); free(J.Q);
   return rc;
 }
+
+/* ------------------------------------------------- layered point cloud */
+/* Layered-point-cloud (LPC) layout: the Potree-style input of the LOD
+ * renderer, produced here the way a converter would produce it (the paper
+ * loads such files; the converter is not part of its method).
+ *
+ *   cube:    the cloud's box min corner and its largest extent (binary64);
+ *   level:   L in 0..depth per point, drawn from SplitMix64(seed, i) with
+ *            P(L) proportional to 4^L (each level roughly quadruples the
+ *            points, like octree levels of a surface);
+ *   node:    (L, octree cell of depth L), the cell from 20-bit-per-axis grid
+ *            coordinates q = min(floor(2^20 (x - min) / size), 2^20 - 1);
+ *   order:   by (L, Morton code of q), stable;
+ *   batches: each node's points in chunks of at most cap, every chunk
+ *            starting at a multiple of 4 (the slots in between are padding,
+ *            zero, in no batch).
+ * Outputs: xyz_out / rgba_out (npad points), spans[2b] = first,
+ * spans[2b + 1] = count, nodes[5b ..] = cube origin x, y, z, edge, level.
+ * Returns 0; -1 bad arguments; -2 no memory; -3 output capacity too small
+ * (*npad_out, *nb_out then hold what is needed). */
+static inline uint64_t spread3_20(uint64_t v) {
+  uint64_t r = 0;
+  for (int b = 0; b < 20; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+  return r;
+}
+static inline uint64_t compact3_20(uint64_t c) {
+  uint64_t r = 0;
+  for (int b = 0; b < 20; ++b) r |= ((c >> (3 * b)) & 1ull) << b;
+  return r;
+}
+
+int synth_lpc_layout(uint64_t seed, const float* xyz, const uint32_t* rgba, uint64_t n, int depth, uint32_t cap,
+                     float* xyz_out, uint32_t* rgba_out, uint64_t cap_points, uint32_t* spans, double* nodes,
+                     uint64_t cap_batches, uint64_t* npad_out, uint64_t* nb_out) {
+  if (!xyz || !rgba || !npad_out || !nb_out || depth < 0 || depth > 15 || cap < 4 || n >= (1ull << 32)) return -1;
+  double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = n ? (double)xyz[a] : 0.0;
+    mx[a] = mn[a];
+  }
+  for (uint64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      double v = (double)xyz[3 * i + a];
+      if (v < mn[a]) mn[a] = v;
+      if (v > mx[a]) mx[a] = v;
+    }
+  double size = 0.0;
+  for (int a = 0; a < 3; ++a)
+    if (mx[a] - mn[a] > size) size = mx[a] - mn[a];
+  if (size == 0.0) size = 1.0;
+  /* level CDF: P(L <= l) = (4^(l+1) - 1) / (4^(depth+1) - 1) */
+  double cdf[16];
+  double tot = 0.0, acc = 0.0;
+  for (int l = 0; l <= depth; ++l) tot += ldexp(1.0, 2 * l);
+  for (int l = 0; l <= depth; ++l) {
+    acc += ldexp(1.0, 2 * l);
+    cdf[l] = acc / tot;
+  }
+  uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+  uint64_t* key2 = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+  uint32_t* idx = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+  uint32_t* idx2 = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+  if (!key || !key2 || !idx || !idx2) {
+    free(key); free(key2); free(idx); free(idx2);
+    return -2;
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    double u = u01(sm_at(seed ^ 0x4C50434C50434C50ull, i));
+    int L = 0;
+    while (L < depth && u >= cdf[L]) ++L;
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      double f = floor((((double)xyz[3 * i + a] - mn[a]) * 1048576.0) / size);
+      q[a] = f >= 1048575.0 ? 1048575u : (f <= 0.0 ? 0u : (uint64_t)f);
+    }
+    key[i] = ((uint64_t)L << 60) | spread3_20(q[0]) | (spread3_20(q[1]) << 1) | (spread3_20(q[2]) << 2);
+    idx[i] = (uint32_t)i;
+  }
+  /* stable LSD radix sort of (key, idx), 8 bits per pass */
+  uint64_t* cnt = (uint64_t*)calloc(256, sizeof(uint64_t));
+  if (!cnt) {
+    free(key); free(key2); free(idx); free(idx2);
+    return -2;
+  }
+  for (int pass = 0; pass < 8; ++pass) {
+    int sh = 8 * pass;
+    memset(cnt, 0, 256 * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; ++i) cnt[(key[i] >> sh) & 255u]++;
+    uint64_t s = 0;
+    for (int d = 0; d < 256; ++d) {
+      uint64_t c = cnt[d];
+      cnt[d] = s;
+      s += c;
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+      uint64_t d = cnt[(key[i] >> sh) & 255u]++;
+      key2[d] = key[i];
+      idx2[d] = idx[i];
+    }
+    uint64_t* tk = key; key = key2; key2 = tk;
+    uint32_t* ti = idx; idx = idx2; idx2 = ti;
+  }
+  free(cnt);
+  /* nodes and batches */
+  uint64_t pos = 0, nb = 0;
+  int fits = 1;
+  uint64_t i = 0;
+  while (i < n) {
+    int L = (int)(key[i] >> 60);
+    uint64_t cell = (key[i] & ((1ull << 60) - 1)) >> (3 * (20 - L));
+    uint64_t j = i;
+    while (j < n && (int)(key[j] >> 60) == L && ((key[j] & ((1ull << 60) - 1)) >> (3 * (20 - L))) == cell) ++j;
+    double edge = ldexp(size, -L);
+    for (uint64_t c0 = i; c0 < j; c0 += cap) {
+      uint64_t c1 = c0 + cap < j ? c0 + cap : j;
+      pos = (pos + 3) & ~3ull;
+      if (nb < cap_batches && pos + (c1 - c0) <= cap_points && xyz_out && rgba_out && spans && nodes) {
+        spans[2 * nb] = (uint32_t)pos;
+        spans[2 * nb + 1] = (uint32_t)(c1 - c0);
+        for (int a = 0; a < 3; ++a) {
+          uint64_t k = compact3_20(cell << (3 * (20 - L)) >> a) >> (20 - L);
+          nodes[5 * nb + a] = mn[a] + (double)k * edge;
+        }
+        nodes[5 * nb + 3] = edge;
+        nodes[5 * nb + 4] = (double)L;
+        for (uint64_t t = c0; t < c1; ++t) {
+          uint64_t s = idx[t], d = pos + (t - c0);
+          xyz_out[3 * d] = xyz[3 * s];
+          xyz_out[3 * d + 1] = xyz[3 * s + 1];
+          xyz_out[3 * d + 2] = xyz[3 * s + 2];
+          rgba_out[d] = rgba[s];
+        }
+      } else {
+        fits = 0;
+      }
+      pos += c1 - c0;
+      ++nb;
+    }
+    i = j;
+  }
+  free(key); free(key2); free(idx); free(idx2);
+  *npad_out = pos;
+  *nb_out = nb;
+  return fits ? 0 : -3;
+}

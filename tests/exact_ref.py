@@ -183,3 +183,37 @@ def brute_force_hqs(xyz_sorted, colors, batch_size, view, proj, w, h, window, pr
                 a1 = (a1 + ((c >> 16) & 255) + (1 << 32)) % M
         out[pix] = (a0, a1)
     return out
+
+
+def brute_force_spans(xyz, spans, view, proj, w, h, precision=0):
+    """As brute_force, for variable-size batches given as (first, count) spans over xyz (render order)."""
+    Pm = frame_matrix(view, proj, w, h)
+    out = {}
+    for first, count in spans:
+        pts = xyz[first:first + count]
+        bmin = [min(float(p[a]) for p in pts) for a in range(3)]
+        bmax = [max(float(p[a]) for p in pts) for a in range(3)]
+        k, P, t = batch_level_and_fold(Pm, bmin, bmax, w, h, precision)
+        for j, p in enumerate(pts):
+            r = point_key(first + j, p, bmin, bmax, k, P, t, w, h)
+            if r is None:
+                continue
+            pix, key = r
+            if pix not in out or key < out[pix]:
+                out[pix] = key
+    return out
+
+
+def cube_extent(view, proj, w, h, origin, edge):
+    """Projected extent of the cube [origin, origin + edge] in exact rationals: the larger side of the screen box
+    of its 8 projected corners, or None if a corner has w <= 0."""
+    Pm = [[Fraction(x) for x in row] for row in frame_matrix(view, proj, w, h)]
+    us, vs = [], []
+    for c in range(8):
+        p = [Fraction(origin[a]) + (Fraction(edge) if (c >> a) & 1 else 0) for a in range(3)]
+        hx, hy, hw = (sum(Pm[r][j] * p[j] for j in range(3)) + Pm[r][3] for r in range(3))
+        if hw <= 0:
+            return None
+        us.append(hx / hw)
+        vs.append(hy / hw)
+    return max(max(us) - min(us), max(vs) - min(vs))

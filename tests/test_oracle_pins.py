@@ -476,3 +476,74 @@ def test_hqs_resolve_rounds_to_nearest():
                    np.uint64)
     fb = oracle.resolve_hqs(acc, 0x12345678)
     assert fb.tolist() == [0xFF040302, 0x12345678, 0xFF0000FF]
+
+
+# ------------------------------------------------------------------ LOD (Sec. 3.5)
+def _lpc_cloud(seed, n, cap=64):
+    rng = np.random.default_rng(seed)
+    xyz = _tiny_cloud(rng, n)
+    rgba = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    depth = synth.lpc_depth(n, cap)
+    xo, ro, spans, nodes = synth.lpc_layout(seed, xyz, rgba, depth, cap)
+    return rng, oracle.build_cloud_spans(xo, ro, spans, nodes), spans, nodes
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_lod_culling_matches_exact_cube_extent(seed):
+    """A node below the root is culled iff its cube's exact projected extent is below lod_px (decisions within a
+    relative 1e-9 of the threshold are not compared)."""
+    rng, B, spans, nodes = _lpc_cloud(400 + seed, 3000)
+    w, h = int(rng.integers(40, 200)), int(rng.integers(40, 200))
+    for _ in range(20):  # a camera that sees some batch below the root
+        cam = synth.random_camera(rng, w, h, box=((0, 0, 0), (10, 10, 10)))
+        d = oracle.decide_all(B.batches, cam.view, cam.proj, w, h, oracle.opts(), nodes)
+        if np.any((d["culled"] == 0) & (nodes[:, 4] >= 1)):
+            break
+    for lod_px in (2.0, 10.0, 40.0):
+        d_lod = oracle.decide_all(B.batches, cam.view, cam.proj, w, h, oracle.opts(lod_px=lod_px), nodes)
+        d_off = oracle.decide_all(B.batches, cam.view, cam.proj, w, h, oracle.opts(), nodes)
+        compared = 0
+        for b in range(len(spans)):
+            if d_off["culled"][b]:
+                assert d_lod["culled"][b]
+                continue
+            if nodes[b, 4] == 0:
+                assert not d_lod["culled"][b]
+                continue
+            E = exact_ref.cube_extent(cam.view.tolist(), cam.proj.tolist(), w, h, nodes[b, :3], nodes[b, 3])
+            if E is not None and abs(float(E) - lod_px) <= 1e-9 * lod_px:
+                continue
+            assert bool(d_lod["culled"][b]) == (E is not None and E < lod_px), (b, E, lod_px)
+            compared += 1
+        assert compared > 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_lod_off_equals_exact_bruteforce_over_spans(seed):
+    rng, B, spans, nodes = _lpc_cloud(500 + seed, 400, cap=32)
+    w, h = int(rng.integers(8, 30)), int(rng.integers(8, 30))
+    cam = synth.random_camera(rng, w, h, inside=bool(seed % 2), box=((0, 0, 0), (10, 10, 10)))
+    vb, _ = oracle.render(B, cam.view, cam.proj, w, h)
+    got = {int(p): int(vb[p]) for p in np.nonzero(vb != oracle.EMPTY)[0]}
+    assert got == exact_ref.brute_force_spans(B.xyz.tolist(), spans.tolist(), cam.view.tolist(), cam.proj.tolist(),
+                                              w, h)
+
+
+def test_lod_renders_exactly_the_surviving_batches_and_is_monotone():
+    rng, B, spans, nodes = _lpc_cloud(600, 4000)
+    cam = synth.random_camera(rng, 160, 120, box=((0, 0, 0), (10, 10, 10)))
+    prev = None
+    for lod_px in (0.0, 5.0, 20.0, 80.0, 1e6):
+        o = oracle.opts(lod_px=lod_px)
+        vb, st = oracle.render(B, cam.view, cam.proj, 160, 120, o)
+        dec = oracle.decide_all(B.batches, cam.view, cam.proj, 160, 120, o, nodes)
+        keep = np.nonzero(dec["culled"] == 0)[0].astype(np.uint64)
+        B_plain = oracle.build_cloud_spans(B.xyz, B.colors, spans)  # no nodes: no LOD culling
+        sub, _ = oracle.render(B_plain, cam.view, cam.proj, 160, 120, batch_ids=keep)
+        assert np.array_equal(vb, sub)
+        assert st["culled"] == int(np.count_nonzero(dec["culled"]))
+        if prev is not None:
+            assert np.all(dec["culled"] >= prev)  # a larger threshold never brings a node back
+        prev = dec["culled"]
+    assert not np.any(dec["culled"][nodes[:, 4] == 0] & (oracle.decide_all(
+        B.batches, cam.view, cam.proj, 160, 120, oracle.opts(), nodes)["culled"] == 0))

@@ -72,3 +72,30 @@ def test_request_stream_is_seeded_and_poisson():
     t = np.array([x for x, _, _ in a])
     assert np.all(np.diff(t) > 0) and 0.6 < t[-1] < 1.0  # 400 arrivals at 500/s take about 0.8 s
     assert {cam.width for _, _, cam in a} == {640, 1920, 3840} and {c for _, c, _ in a} == {0, 1, 2}
+
+
+def test_lpc_layout_properties():
+    xyz, rgba = synth.terrain(7, 200_000, order=1)
+    cap = 2048
+    depth = synth.lpc_depth(len(xyz), cap)
+    xo, ro, spans, nodes = synth.lpc_layout(3, xyz, rgba, depth, cap)
+    again = synth.lpc_layout(3, xyz, rgba, depth, cap)
+    assert all(np.array_equal(a, b) for a, b in zip((xo, ro, spans, nodes), again))
+    first, count = spans[:, 0].astype(np.int64), spans[:, 1].astype(np.int64)
+    assert np.all(first % 4 == 0) and np.all(count >= 1) and np.all(count <= cap)
+    assert np.all(first[1:] >= first[:-1] + count[:-1])  # ordered, disjoint
+    idx = np.concatenate([np.arange(f, f + c) for f, c in zip(first, count)])
+    # every input point exactly once
+    a = np.rec.fromarrays([xyz[:, 0], xyz[:, 1], xyz[:, 2], rgba])
+    b = np.rec.fromarrays([xo[idx, 0], xo[idx, 1], xo[idx, 2], ro[idx]])
+    assert np.array_equal(np.sort(a), np.sort(b))
+    pad = np.setdiff1d(np.arange(len(xo)), idx)
+    assert np.all(xo[pad] == 0) and np.all(ro[pad] == 0)
+    # batches lie in their node's cube (up to one ulp of the grid), levels deepen in order
+    for (f, c), nd in zip(spans[::7], nodes[::7]):
+        p = xo[f:f + c].astype(np.float64)
+        tol = 1e-6 * nd[3] + 1e-6
+        assert np.all(p >= nd[:3] - tol) and np.all(p <= nd[:3] + nd[3] + tol)
+    assert np.all(np.diff(nodes[:, 4]) >= 0) and nodes[0, 4] == 0
+    pts = np.bincount(nodes[:, 4].astype(int), weights=count)
+    assert np.all(pts[1:-1] / pts[:-2] > 3.0) and np.all(pts[1:-1] / pts[:-2] < 5.0)  # about 4x per level
