@@ -67,9 +67,16 @@ typedef struct {
   float min[3], max[3];
 } pr_batch;
 
+/* Octree node of a batch in a level-of-detail layout (Sec. 3.5): the node's
+ * cube (origin and edge, binary64) and its level (0 = root).  48 bytes. */
+typedef struct {
+  double origin[3], edge;
+  uint32_t level, pad[3];
+} pr_lod_node;
+
 /* Byte sizes of the cloud buffers; see pr_cloud_bufs. */
 typedef struct {
-  uint64_t xyz, rgba, low, med, high, colors, perm, batches, scratch;
+  uint64_t xyz, rgba, low, med, high, colors, perm, batches, scratch, nodes;
 } pr_sizes;
 
 /* Caller-allocated device buffers of one cloud (each 256-byte aligned).
@@ -82,12 +89,15 @@ typedef struct {
  *   colors  uint32[n]     colours in render order
  *   perm    uint32[n]     perm[render index] = input index
  *   batches pr_batch[nb]  nb = ceil(n / batch_size)
- *   scratch               load-time working memory (Morton sort)
+ *   scratch               load-time working memory (Morton sort) and the
+ *                         frame work area of pr_render
+ *   nodes   pr_lod_node[nb] LOD layouts only (pr_build_batches_spans); may
+ *                         be NULL otherwise
  * capacity must hold the sizes the caller allocated (normally the output of
  * pr_cloud_sizes); pr_build_batches checks it and fails with PR_EINVAL if a
  * buffer is too small for (n, batch_size, morton). */
 typedef struct {
-  void *xyz, *rgba, *low, *med, *high, *colors, *perm, *batches, *scratch;
+  void *xyz, *rgba, *low, *med, *high, *colors, *perm, *batches, *scratch, *nodes;
   pr_sizes capacity;
 } pr_cloud_bufs;
 
@@ -101,6 +111,10 @@ typedef struct {
   int32_t accumulate;/* 1: do not clear visbuf first; points combine with its content by
                         minimum, so a sequence of renders into one buffer equals the
                         elementwise minimum of the separate results [0]               */
+  float lod_px;      /* LOD layouts (Sec. 3.5): > 0 culls every batch of a node below the
+                        root whose cube projects to less than lod_px pixels (the larger
+                        side of the screen box of its 8 corners; a cube reaching w <= 0 is
+                        kept) [0 = no LOD culling; the paper suggests 100]             */
 } pr_render_opts;
 
 /* Frame counters (Table 2 definitions): processed batches = every batch,
@@ -126,6 +140,10 @@ void pr_destroy(pr_ctx* ctx);
  * (multiple of 4), with or without the Morton sort (Sec. 3.1).  Pure host
  * arithmetic; needs no GPU. */
 pr_status pr_cloud_sizes(uint64_t n, uint32_t batch_size, int morton, pr_sizes* out);
+
+/* Byte sizes for a cloud of n point slots in nb variable-size batches
+ * (pr_build_batches_spans): no Morton scratch, a nodes buffer. */
+pr_status pr_cloud_sizes_spans(uint64_t n, uint64_t nb, pr_sizes* out);
 
 /* Copy n positions (float[n][3]) and colours (uint32[n]) into bufs->xyz and
  * bufs->rgba (skipped where source and destination coincide), from host
@@ -173,6 +191,19 @@ pr_status pr_views_work_bytes(const pr_cloud* cloud, uint32_t nviews, uint64_t* 
  * matrices, PR_ESTATE before pr_build_batches. */
 pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
                           const pr_render_opts* opts, void* work, uint64_t work_bytes);
+
+/* Load-time build of a level-of-detail layout (Sec. 3.5): the points are
+ * already in render order (a layered point cloud: octree nodes level by
+ * level) and grouped into nb variable-size batches given on the host as
+ * spans[2b] = first point, spans[2b + 1] = number of points (first a multiple
+ * of 4, spans ascending and disjoint, inside the cloud; slots between batches
+ * are padding and never read).  nodes (host, may be NULL): the octree node of
+ * each batch, copied to bufs->nodes for LOD culling at render time.  Checks
+ * every coordinate is finite, computes each batch's fp32 box and the Eq. 1
+ * words.  Synchronises once.  PR_EINVAL for bad spans or small buffers,
+ * PR_ENONFINITE for NaN / Inf coordinates. */
+pr_status pr_build_batches_spans(pr_ctx* ctx, pr_cloud* cloud, const uint32_t* spans, const pr_lod_node* nodes,
+                                 uint64_t nb);
 
 /* Fill visbuf (uint64[h*w], device, 16-byte aligned) with PR_EMPTY (the
  * frame clear of Sec. 4.3).  Asynchronous. */

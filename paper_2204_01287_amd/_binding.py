@@ -24,7 +24,8 @@ _STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "
 
 EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_load_points", "pr_build_batches",
             "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
-            "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers", "pr_render_hqs"]
+            "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers", "pr_render_hqs",
+            "pr_cloud_sizes_spans", "pr_build_batches_spans"]
 
 
 class PrError(RuntimeError):
@@ -34,24 +35,30 @@ class PrError(RuntimeError):
         super().__init__(f"{where}: {self.name}: {pr_last_error()}")
 
 
+BUFFER_FIELDS = ("xyz", "rgba", "low", "med", "high", "colors", "perm", "batches", "scratch", "nodes")
+
+
 class Sizes(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_uint64) for n in
-                ("xyz", "rgba", "low", "med", "high", "colors", "perm", "batches", "scratch")]
+    _fields_ = [(n, ctypes.c_uint64) for n in BUFFER_FIELDS]
 
 
 class CloudBufs(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in
-                ("xyz", "rgba", "low", "med", "high", "colors", "perm", "batches", "scratch")] + \
-               [("capacity", Sizes)]
+    _fields_ = [(n, ctypes.c_void_p) for n in BUFFER_FIELDS] + [("capacity", Sizes)]
+
+
+class LodNode(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("edge", ctypes.c_double), ("level", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32 * 3)]
 
 
 class RenderOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cull", ctypes.c_int32), ("t10", ctypes.c_float),
-                ("t20", ctypes.c_float), ("counters", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+                ("t20", ctypes.c_float), ("counters", ctypes.c_int32), ("accumulate", ctypes.c_int32),
+                ("lod_px", ctypes.c_float)]
 
     @classmethod
-    def make(cls, precision=PR_ADAPTIVE, cull=1, t10=500.0, t20=512000.0, counters=0, accumulate=0):
-        return cls(precision, cull, t10, t20, counters, accumulate)
+    def make(cls, precision=PR_ADAPTIVE, cull=1, t10=500.0, t20=512000.0, counters=0, accumulate=0, lod_px=0.0):
+        return cls(precision, cull, t10, t20, counters, accumulate, lod_px)
 
 
 class View(ctypes.Structure):
@@ -85,6 +92,8 @@ lib.pr_resolve.argtypes = [_P, _P, _P, _U32, _U32, _U32, _P]
 lib.pr_get_stats.argtypes = [_P, ctypes.POINTER(Stats)]
 lib.pr_views_work_bytes.argtypes = [_P, _U32, ctypes.POINTER(_U64)]
 lib.pr_cloud_drop_load_buffers.argtypes = [_P]
+lib.pr_cloud_sizes_spans.argtypes = [_U64, _U64, ctypes.POINTER(Sizes)]
+lib.pr_build_batches_spans.argtypes = [_P, _P, _P, _P, _U64]
 lib.pr_render_hqs.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts), ctypes.c_float, _P, _P, _U32, _P]
 lib.pr_render_views.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64]
 lib.pr_sync.argtypes = [_P]
@@ -93,7 +102,7 @@ lib.pr_cloud_free.argtypes = [_P]
 lib.pr_cloud_free.restype = None
 for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
            "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views",
-           "pr_cloud_drop_load_buffers", "pr_render_hqs"):
+           "pr_cloud_drop_load_buffers", "pr_render_hqs", "pr_cloud_sizes_spans", "pr_build_batches_spans"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -163,6 +172,32 @@ def pr_render(ctx, cloud, view, proj, w: int, h: int, opts: RenderOpts | None, v
     p, pp = _mat16(proj)
     _check(lib.pr_render(ctx, cloud, vp, pp, w, h, ctypes.byref(opts) if opts is not None else None, _ptr(visbuf)),
            "pr_render")
+
+
+def pr_cloud_sizes_spans(n: int, nb: int) -> Sizes:
+    s = Sizes()
+    _check(lib.pr_cloud_sizes_spans(n, nb, ctypes.byref(s)), "pr_cloud_sizes_spans")
+    return s
+
+
+def lod_nodes(nodes) -> ctypes.Array:
+    """LodNode array from a float64 (nb, 5) table: cube origin x, y, z, edge, level."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    arr = (LodNode * len(nodes))()
+    for i, row in enumerate(nodes):
+        arr[i].origin[:] = [float(row[0]), float(row[1]), float(row[2])]
+        arr[i].edge = float(row[3])
+        arr[i].level = int(row[4])
+    return arr
+
+
+def pr_build_batches_spans(ctx, cloud, spans, nodes=None):
+    """spans: uint32 (nb, 2) = first, count; nodes: float64 (nb, 5) or None."""
+    sp = np.ascontiguousarray(np.asarray(spans, dtype=np.uint32).reshape(-1, 2))
+    nd = lod_nodes(nodes) if nodes is not None else None
+    _check(lib.pr_build_batches_spans(ctx, cloud, sp.ctypes.data if len(sp) else None,
+                                      ctypes.cast(nd, ctypes.c_void_p) if nd is not None else None, len(sp)),
+           "pr_build_batches_spans")
 
 
 def pr_cloud_drop_load_buffers(cloud):
@@ -244,14 +279,21 @@ class Context:
 class DeviceCloud:
     """Cloud buffers allocated as torch tensors (sized by pr_cloud_sizes), loaded and built."""
 
-    FIELDS = ("xyz", "rgba", "low", "med", "high", "colors", "perm", "batches", "scratch")
+    FIELDS = BUFFER_FIELDS
 
-    def __init__(self, ctx: Context, xyz, rgba, batch_size: int = 10240, morton: bool = False):
+    def __init__(self, ctx: Context, xyz, rgba, batch_size: int = 10240, morton: bool = False, spans=None,
+                 nodes=None):
+        """Fixed-size batches of batch_size points (optionally Morton-sorted), or, with spans (uint32 (nb, 2) =
+        first, count), the variable-size batches of a level-of-detail layout with optional nodes (float64 (nb, 5))."""
         import torch
 
         n = int(xyz.shape[0])
         self.ctx, self.n, self.batch_size, self.morton = ctx, n, batch_size, morton
-        self.sizes = pr_cloud_sizes(n, batch_size, morton)
+        if spans is not None:
+            spans = np.ascontiguousarray(np.asarray(spans, dtype=np.uint32).reshape(-1, 2))
+            self.sizes = pr_cloud_sizes_spans(n, len(spans))
+        else:
+            self.sizes = pr_cloud_sizes(n, batch_size, morton)
         dev = torch.device("cuda", ctx.device)
         self.mem = {f: torch.empty(max(getattr(self.sizes, f), 256), dtype=torch.uint8, device=dev)
                     for f in self.FIELDS}
@@ -262,7 +304,10 @@ class DeviceCloud:
             rgba = np.ascontiguousarray(rgba, dtype=np.uint32)
         self._src = (xyz, rgba)  # keep host sources alive until the copies are done
         self.handle = pr_load_points(ctx.handle, xyz, rgba, n, on_dev, self.bufs)
-        pr_build_batches(ctx.handle, self.handle, batch_size, morton)
+        if spans is not None:
+            pr_build_batches_spans(ctx.handle, self.handle, spans, nodes)
+        else:
+            pr_build_batches(ctx.handle, self.handle, batch_size, morton)
         self._src = None
         self.nb = pr_cloud_info(self.handle)[1]
 

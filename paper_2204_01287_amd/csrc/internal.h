@@ -12,6 +12,13 @@ struct BatchRec {  // identical layout to pr_batch
 };
 static_assert(sizeof(BatchRec) == 32, "batch record is 32 bytes");
 
+// Octree node of a batch in a level-of-detail layout (identical layout to pr_lod_node).
+struct LodNode {
+  double origin[3], edge;
+  uint32_t level, pad[3];
+};
+static_assert(sizeof(LodNode) == 48, "LOD node record is 48 bytes");
+
 // Device-side context block (one per pr_ctx), 4 KiB.
 struct DevBlock {
   uint64_t stats[16];     // batches, culled, points, lvl_b[3], lvl_p[3], atomics
@@ -60,6 +67,8 @@ struct RenderArgs {
   int32_t precision, cull, counters;
   float t10, t20;
   uint32_t grid;    // persistent render workgroups
+  const LodNode* nodes;  // LOD layouts: node per batch (else nullptr)
+  float lod_px;          // > 0: cull nodes below the root whose cube projects below lod_px pixels
   // high-quality shading pass only
   const uint32_t* colors;
   uint64_t* accum;  // two words per pixel
@@ -94,6 +103,8 @@ struct ClassifyViewsArgs {
   uint32_t nb, nviews, view0, nchunk;  // all views, first view of this launch, views in it
   int32_t precision, cull;
   float t10, t20;
+  const LodNode* nodes;
+  float lod_px;
   ViewIn v[VIEW_CHUNK];
 };
 struct RenderViewsArgs {
@@ -160,6 +171,10 @@ hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, 
 hipError_t launch_gather(const float* xyz, const uint32_t* rgba, const uint32_t* perm, uint64_t n, float* xyz_out,
                          uint32_t* colors, hipStream_t s);
 hipError_t launch_batch_bbox(const float* xyz, uint64_t n, uint32_t S, uint64_t nb, BatchRec* out, hipStream_t s);
+// variable-size batches: recs[b].first / .count are set, the boxes are filled in
+hipError_t launch_batch_bbox_spans(const float* xyz, uint64_t nb, BatchRec* recs, hipStream_t s);
+hipError_t launch_quantize_spans(const float* xyz, uint64_t nb, const BatchRec* recs, uint32_t* low, uint32_t* med,
+                                 uint32_t* high, hipStream_t s);
 hipError_t launch_quantize(const float* xyz, uint64_t n, uint32_t S, const BatchRec* batches, uint32_t* low,
                            uint32_t* med, uint32_t* high, hipStream_t s);
 

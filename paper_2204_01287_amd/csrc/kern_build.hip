@@ -251,10 +251,12 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ xyz, c
 }
 
 // ------------------------------------------------------------ batch boxes
+// One block per batch: batch b is [b S, min((b + 1) S, n)), or, with spans,
+// [out[b].first, out[b].first + out[b].count) as set by the host.
 __global__ void __launch_bounds__(256) k_batch_bbox(const float* __restrict__ xyz, uint64_t n, uint32_t S,
-                                                    BatchRec* __restrict__ out) {
-  const uint64_t first = (uint64_t)blockIdx.x * S;
-  const uint64_t end = first + S < n ? first + S : n;
+                                                    BatchRec* __restrict__ out, int spans) {
+  const uint64_t first = spans ? out[blockIdx.x].first : (uint64_t)blockIdx.x * S;
+  const uint64_t end = spans ? first + out[blockIdx.x].count : (first + S < n ? first + S : n);
   uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0, 0, 0};
   for (uint64_t i = first + threadIdx.x; i < end; i += 256) {
 #pragma unroll
@@ -315,6 +317,27 @@ __global__ void __launch_bounds__(256) k_quantize(const float* __restrict__ xyz,
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const BatchRec& B = batches[(uint32_t)i / S];  // i < 2^32
+    uint32_t lw = 0, mw = 0, hw = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const uint32_t X30 = eq1(xyz[3 * i + a], B.mn[a], B.mx[a]);
+      lw |= ((X30 >> 20) & 1023u) << (10 * a);
+      mw |= ((X30 >> 10) & 1023u) << (10 * a);
+      hw |= (X30 & 1023u) << (10 * a);
+    }
+    low[i] = lw;
+    med[i] = mw;
+    high[i] = hw;
+  }
+}
+
+// Variable-size batches: one block per batch, Eq. 1 relative to its box.
+__global__ void __launch_bounds__(256) k_quantize_spans(const float* __restrict__ xyz,
+                                                        const BatchRec* __restrict__ batches,
+                                                        uint32_t* __restrict__ low, uint32_t* __restrict__ med,
+                                                        uint32_t* __restrict__ high) {
+  const BatchRec B = batches[blockIdx.x];
+  for (uint64_t i = (uint64_t)B.first + threadIdx.x; i < (uint64_t)B.first + B.count; i += 256) {
     uint32_t lw = 0, mw = 0, hw = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -420,13 +443,26 @@ hipError_t launch_gather(const float* xyz, const uint32_t* rgba, const uint32_t*
 
 hipError_t launch_batch_bbox(const float* xyz, uint64_t n, uint32_t S, uint64_t nb, BatchRec* out, hipStream_t s) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_bbox, dim3((uint32_t)nb), dim3(256), 0, s, xyz, n, S, out);
+  hipLaunchKernelGGL(k_batch_bbox, dim3((uint32_t)nb), dim3(256), 0, s, xyz, n, S, out, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_quantize(const float* xyz, uint64_t n, uint32_t S, const BatchRec* batches, uint32_t* low,
                            uint32_t* med, uint32_t* high, hipStream_t s) {
   hipLaunchKernelGGL(k_quantize, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, xyz, n, S, batches, low, med, high);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bbox_spans(const float* xyz, uint64_t nb, BatchRec* recs, hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_bbox, dim3((uint32_t)nb), dim3(256), 0, s, xyz, (uint64_t)0, 0u, recs, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize_spans(const float* xyz, uint64_t nb, const BatchRec* recs, uint32_t* low, uint32_t* med,
+                                 uint32_t* high, hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quantize_spans, dim3((uint32_t)nb), dim3(256), 0, s, xyz, recs, low, med, high);
   return hipGetLastError();
 }
 

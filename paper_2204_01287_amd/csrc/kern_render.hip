@@ -403,9 +403,36 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
 //           t[r] = fp32(((Pm[r][0] min_x + Pm[r][1] min_y) + Pm[r][2] min_z) + Pm[r][3]).
 // decide_batch applies it to one batch and one view: returns whether the
 // batch is live; out receives its render record, li its level index.
+// Projected extent of the cube of a LOD node (8 corners, binary64, left to
+// right): +inf if a corner has w <= 0, else the larger side of the screen box
+// of the projected corners.
+__device__ __forceinline__ double cube_extent(const double (&Pm)[3][4], const LodNode& nd) {
+  double umin = __builtin_inf(), umax = -__builtin_inf(), vmin = __builtin_inf(), vmax = -__builtin_inf();
+  for (int c = 0; c < 8; ++c) {
+    const double cx = (c & 1) ? nd.origin[0] + nd.edge : nd.origin[0];
+    const double cy = (c & 2) ? nd.origin[1] + nd.edge : nd.origin[1];
+    const double cz = (c & 4) ? nd.origin[2] + nd.edge : nd.origin[2];
+    const double hx = ((Pm[0][0] * cx + Pm[0][1] * cy) + Pm[0][2] * cz) + Pm[0][3];
+    const double hy = ((Pm[1][0] * cx + Pm[1][1] * cy) + Pm[1][2] * cz) + Pm[1][3];
+    const double hw = ((Pm[2][0] * cx + Pm[2][1] * cy) + Pm[2][2] * cz) + Pm[2][3];
+    if (!(hw > 0.0)) return __builtin_inf();
+    const double u = hx / hw, v = hy / hw;
+    umin = fmin(umin, u);
+    umax = fmax(umax, u);
+    vmin = fmin(vmin, v);
+    vmax = fmax(vmax, v);
+  }
+  const double ex = umax - umin, ey = vmax - vmin;
+  return ex > ey ? ex : ey;
+}
+
+// node: the batch's LOD node or nullptr.  LOD culling (Sec. 3.5): with
+// lod_px > 0, a batch of a node below the root is culled iff its node's cube
+// projects to less than lod_px pixels.
 __device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (&Pm)[3][4], uint32_t W, uint32_t Hh,
-                                             int32_t precision, int32_t cull, float t10, float t20, LiveBatch& out,
-                                             bool& culled, int& li) {
+                                             int32_t precision, int32_t cull, float t10, float t20,
+                                             const LodNode* node, float lod_px, LiveBatch& out, bool& culled,
+                                             int& li) {
   bool live = false;
   double H[3][8], M[3];
 #pragma unroll
@@ -439,6 +466,7 @@ __device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (
           (H[1][c] - Hd * H[2][c] < -(M[1] + Hd * M[2]));
   }
   culled = cull && (behind || left || right || bottom || top);
+  if (!culled && lod_px > 0.0f && node && node->level > 0) culled = cube_extent(Pm, *node) < (double)lod_px;
   if (!culled) {
     double umin = __builtin_inf(), umax = -__builtin_inf(), vmin = __builtin_inf(), vmax = -__builtin_inf();
     if (front) {
@@ -525,7 +553,8 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
   if (valid) {
     const BatchRec rec = a.batches[b];
     count = rec.count;
-    live = decide_batch(rec, a.Pm, a.W, a.H, a.precision, a.cull, a.t10, a.t20, out, culled, li);
+    live = decide_batch(rec, a.Pm, a.W, a.H, a.precision, a.cull, a.t10, a.t20, a.nodes ? a.nodes + b : nullptr,
+                        a.lod_px, out, culled, li);
   }
   if constexpr (CNT) {
     const uint64_t mv = __ballot(valid), mc = __ballot(valid && culled);
@@ -577,7 +606,8 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
       LiveBatch out;
       bool culled = false;
       int li = 0;
-      if (decide_batch(rec, a.v[v].Pm, a.v[v].W, a.v[v].H, a.precision, a.cull, a.t10, a.t20, out, culled, li)) {
+      if (decide_batch(rec, a.v[v].Pm, a.v[v].W, a.v[v].H, a.precision, a.cull, a.t10, a.t20,
+                       a.nodes ? a.nodes + b : nullptr, a.lod_px, out, culled, li)) {
         a.sub[(uint64_t)b * a.nviews + a.view0 + v] = out;
         mask |= 1ull << v;
         if constexpr (CNT) {

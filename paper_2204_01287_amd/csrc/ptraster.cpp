@@ -11,8 +11,12 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
+
+static_assert(sizeof(pr_lod_node) == sizeof(ptr::LodNode), "LOD node layout");
+static_assert(sizeof(pr_batch) == sizeof(ptr::BatchRec), "batch record layout");
 
 struct pr_ctx {
   int device;
@@ -30,7 +34,8 @@ struct pr_cloud {
   uint32_t batch_size;
   int morton;
   int built;
-  int load_dropped;  // xyz, rgba, perm and scratch released by the caller: pr_render_views / pr_resolve only
+  int load_dropped;
+  int lod;           // built from spans with LOD nodes  // xyz, rgba, perm and scratch released by the caller: pr_render_views / pr_resolve only
   pr_cloud_bufs bufs;
 };
 
@@ -111,6 +116,19 @@ pr_status sizes_for(uint64_t n, uint32_t batch_size, int morton, pr_sizes* s) {
   const uint64_t sort = morton ? ptr::sort_scratch_layout(n, nullptr, nullptr) : 0;
   const uint64_t frame = ptr::frame_area_bytes(nb);
   s->scratch = a256(ptr::small_scratch_bytes() + (sort > frame ? sort : frame));
+  s->nodes = 0;
+  return PR_OK;
+}
+
+pr_status sizes_spans(uint64_t n, uint64_t nb, pr_sizes* s) {
+  if (n > kMaxPoints - 1) return fail(PR_ERANGE, "n = %llu point slots: at most 2^32 - 1", (unsigned long long)n);
+  if (nb > n) return fail(PR_EINVAL, "%llu batches for %llu point slots", (unsigned long long)nb, (unsigned long long)n);
+  s->xyz = a256(12 * n);
+  s->rgba = a256(4 * n);
+  s->low = s->med = s->high = s->colors = s->perm = a256(4 * n);
+  s->batches = a256(32 * nb);
+  s->scratch = a256(ptr::small_scratch_bytes() + ptr::frame_area_bytes(nb));
+  s->nodes = a256(sizeof(ptr::LodNode) * nb);
   return PR_OK;
 }
 
@@ -192,8 +210,83 @@ pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, ui
   c->morton = 0;
   c->built = 0;
   c->load_dropped = 0;
+  c->lod = 0;
   c->bufs = *bufs;
   *out = c;
+  return PR_OK;
+}
+
+pr_status pr_cloud_sizes_spans(uint64_t n, uint64_t nb, pr_sizes* out) {
+  if (!out) return fail(PR_EINVAL, "pr_cloud_sizes_spans: out is NULL");
+  return sizes_spans(n, nb, out);
+}
+
+pr_status pr_build_batches_spans(pr_ctx* ctx, pr_cloud* cloud, const uint32_t* spans, const pr_lod_node* nodes,
+                                 uint64_t nb) {
+  if (!ctx || !cloud || (nb && !spans)) return fail(PR_EINVAL, "pr_build_batches_spans: NULL argument");
+  if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_build_batches_spans: cloud belongs to another context");
+  if (cloud->load_dropped) return fail(PR_ESTATE, "pr_build_batches_spans: the cloud's load buffers were released");
+  const uint64_t n = cloud->n;
+  pr_sizes need;
+  if (pr_status s = sizes_spans(n, nb, &need)) return s;
+  uint64_t end = 0;
+  for (uint64_t b = 0; b < nb; ++b) {
+    const uint64_t f = spans[2 * b], c = spans[2 * b + 1];
+    if ((f & 3u) || f < end || c == 0 || f + c > n)
+      return fail(PR_EINVAL, "pr_build_batches_spans: span %llu (first %llu, count %llu) must start at a multiple "
+                  "of 4 after the previous span, hold at least one point and lie inside the %llu slots",
+                  (unsigned long long)b, (unsigned long long)f, (unsigned long long)c, (unsigned long long)n);
+    end = f + c;
+  }
+  const pr_cloud_bufs& B = cloud->bufs;
+  const pr_sizes& cap = B.capacity;
+  if (cap.low < need.low || cap.med < need.med || cap.high < need.high || cap.colors < need.colors ||
+      cap.perm < need.perm || cap.batches < need.batches || cap.scratch < need.scratch ||
+      (nodes && cap.nodes < need.nodes))
+    return fail(PR_EINVAL, "pr_build_batches_spans: a cloud buffer is smaller than pr_cloud_sizes_spans requires");
+  if (n > 0) {
+    const void* ptrs[] = {B.xyz, B.rgba, B.low, B.med, B.high, B.colors, B.perm, B.batches, B.scratch};
+    for (const void* p : ptrs)
+      if (!p || !aligned256(p)) return fail(PR_EINVAL, "pr_build_batches_spans: NULL or unaligned cloud buffer");
+  }
+  if (nodes && nb && (!B.nodes || !aligned256(B.nodes)))
+    return fail(PR_EINVAL, "pr_build_batches_spans: NULL or unaligned nodes buffer");
+  if (pr_status s = set_device(ctx)) return s;
+  hipStream_t st = ctx->stream;
+  cloud->built = 0;
+  std::vector<ptr::BatchRec> recs(nb);
+  for (uint64_t b = 0; b < nb; ++b) {
+    std::memset(&recs[b], 0, sizeof recs[b]);
+    recs[b].first = spans[2 * b];
+    recs[b].count = spans[2 * b + 1];
+  }
+  uint32_t* flag = &ctx->dev->flags[0];
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(uint32_t), st), "clear flag");
+  if (n > 0) {
+    const float* xyz = static_cast<const float*>(B.xyz);
+    HIP_TRY(ptr::launch_finite_check(xyz, n, flag, st), "finite check");
+    HIP_TRY(ptr::launch_iota(static_cast<uint32_t*>(B.perm), n, st), "iota");
+    HIP_TRY(hipMemcpyAsync(B.colors, B.rgba, 4 * n, hipMemcpyDeviceToDevice, st), "copy colours");
+    ptr::BatchRec* dbat = static_cast<ptr::BatchRec*>(B.batches);
+    if (nb) {
+      HIP_TRY(hipMemcpyAsync(dbat, recs.data(), sizeof(ptr::BatchRec) * nb, hipMemcpyHostToDevice, st), "spans");
+      HIP_TRY(ptr::launch_batch_bbox_spans(xyz, nb, dbat, st), "batch boxes");
+      HIP_TRY(ptr::launch_quantize_spans(xyz, nb, dbat, static_cast<uint32_t*>(B.low), static_cast<uint32_t*>(B.med),
+                                         static_cast<uint32_t*>(B.high), st),
+              "quantise");
+      if (nodes)
+        HIP_TRY(hipMemcpyAsync(B.nodes, nodes, sizeof(pr_lod_node) * nb, hipMemcpyHostToDevice, st), "nodes");
+    }
+  }
+  uint32_t h_flag = 0;
+  HIP_TRY(hipMemcpyAsync(&h_flag, flag, sizeof h_flag, hipMemcpyDeviceToHost, st), "read flag");
+  HIP_TRY(hipStreamSynchronize(st), "build");
+  if (h_flag) return fail(PR_ENONFINITE, "pr_build_batches_spans: a coordinate is NaN or Inf");
+  cloud->nb = nb;
+  cloud->batch_size = 0;
+  cloud->morton = 0;
+  cloud->lod = nodes ? 1 : 0;
+  cloud->built = 1;
   return PR_OK;
 }
 
@@ -259,6 +352,7 @@ pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, in
   cloud->nb = nb;
   cloud->batch_size = batch_size;
   cloud->morton = morton ? 1 : 0;
+  cloud->lod = 0;
   cloud->built = 1;
   return PR_OK;
 }
@@ -276,12 +370,13 @@ pr_status check_render(const char* fn, pr_ctx* ctx, const pr_cloud* cloud, const
                 fn);
   if (pr_status s = check_dims(w, h)) return s;
   if (reinterpret_cast<uintptr_t>(visbuf) & 15u) return fail(PR_EINVAL, "%s: visbuf must be 16-byte aligned", fn);
-  *o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0};
+  *o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0, 0.0f};
   if (opts) *o = *opts;
   if (o->precision != PR_ADAPTIVE && o->precision != PR_FORCE10 && o->precision != PR_FORCE20 &&
       o->precision != PR_FORCE30)
     return fail(PR_EINVAL, "%s: precision %d is not 0, 10, 20 or 30", fn, o->precision);
-  if (std::isnan(o->t10) || std::isnan(o->t20)) return fail(PR_EINVAL, "%s: NaN threshold", fn);
+  if (std::isnan(o->t10) || std::isnan(o->t20) || !(o->lod_px >= 0.0f) || !std::isfinite(o->lod_px))
+    return fail(PR_EINVAL, "%s: NaN threshold or lod_px not finite and >= 0", fn);
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(view[i]) || !std::isfinite(proj[i])) return fail(PR_ENONFINITE, "%s: non-finite matrix", fn);
   return set_device(ctx);
@@ -315,6 +410,8 @@ pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16],
   a.counters = o.counters ? 1 : 0;
   a.t10 = o.t10;
   a.t20 = o.t20;
+  a.nodes = cloud->lod ? static_cast<const ptr::LodNode*>(cloud->bufs.nodes) : nullptr;
+  a.lod_px = o.lod_px;
   HIP_TRY(ptr::launch_render(a, ctx->stream), "render");
   return PR_OK;
 }
@@ -376,12 +473,13 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
   if (work_bytes < ptr::views_work_bytes(cloud->nb, nviews))
     return fail(PR_EINVAL, "pr_render_views: work holds %llu bytes, %llu needed", (unsigned long long)work_bytes,
                 (unsigned long long)ptr::views_work_bytes(cloud->nb, nviews));
-  pr_render_opts o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0};
+  pr_render_opts o = {PR_ADAPTIVE, 1, 500.0f, 512000.0f, 0, 0, 0.0f};
   if (opts) o = *opts;
   if (o.precision != PR_ADAPTIVE && o.precision != PR_FORCE10 && o.precision != PR_FORCE20 &&
       o.precision != PR_FORCE30)
     return fail(PR_EINVAL, "pr_render_views: precision %d is not 0, 10, 20 or 30", o.precision);
-  if (std::isnan(o.t10) || std::isnan(o.t20)) return fail(PR_EINVAL, "pr_render_views: NaN threshold");
+  if (std::isnan(o.t10) || std::isnan(o.t20) || !(o.lod_px >= 0.0f) || !std::isfinite(o.lod_px))
+    return fail(PR_EINVAL, "pr_render_views: NaN threshold or lod_px not finite and >= 0");
   for (uint32_t v = 0; v < nviews; ++v) {
     const pr_view& pv = views[v];
     if (!pv.visbuf) return fail(PR_EINVAL, "pr_render_views: view %u has no visbuf", v);
@@ -425,6 +523,8 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
     k.cull = o.cull ? 1 : 0;
     k.t10 = o.t10;
     k.t20 = o.t20;
+    k.nodes = cloud->lod ? static_cast<const ptr::LodNode*>(cloud->bufs.nodes) : nullptr;
+    k.lod_px = o.lod_px;
     for (uint32_t v = 0; v < k.nchunk; ++v) {
       const pr_view& pv = views[k.view0 + v];
       frame_matrix(pv.view, pv.proj, pv.w, pv.h, k.v[v].Pm);

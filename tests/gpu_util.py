@@ -47,7 +47,7 @@ def gpu_build_outputs(dc):
 
 
 def gpu_render(ctx, dc, view, proj, w, h, precision=0, cull=1, counters=1, t10=500.0, t20=512000.0,
-               clear_rgba=0, vb=None, fb=None):
+               clear_rgba=0, vb=None, fb=None, lod_px=0.0):
     import torch
     import paper_2204_01287_amd as pr
 
@@ -55,7 +55,7 @@ def gpu_render(ctx, dc, view, proj, w, h, precision=0, cull=1, counters=1, t10=5
         vb = torch.empty(w * h, dtype=torch.int64, device=torch_dev())
     if fb is None:
         fb = torch.empty(w * h, dtype=torch.int32, device=torch_dev())
-    opts = pr.RenderOpts.make(precision=precision, cull=cull, t10=t10, t20=t20, counters=counters)
+    opts = pr.RenderOpts.make(precision=precision, cull=cull, t10=t10, t20=t20, counters=counters, lod_px=lod_px)
     pr.pr_render(ctx.handle, dc.handle, view, proj, w, h, opts, vb)
     pr.pr_resolve(ctx.handle, dc.handle, vb, w, h, clear_rgba, fb)
     stats = pr.pr_get_stats(ctx.handle) if counters else None
