@@ -265,6 +265,66 @@ def hqs_leg(pr, ctx, cloud, cams, processed, steps, warmup, window=1.01):
     return res
 
 
+def lod_leg(pr, ctx, n: int, steps: int, warmup: int):
+    """Level of detail (Sec. 3.5): the terrain as a layered point cloud (a seeded level per point, octree nodes,
+    variable-size batches of at most 10,240 points), rendered with every node and with the nodes below the root
+    culled under 100 px; the stereo pair and a 1920x1080 orbit overview."""
+    import numpy as np
+    import torch
+    import synth
+
+    t0 = time.perf_counter()
+    xyz, rgba = synth.terrain(synth.C3_SEED, n, order=0)
+    depth = synth.lpc_depth(n, 10240)
+    xo, ro, spans, nodes = synth.lpc_layout(7, xyz, rgba, depth, 10240)
+    del xyz, rgba
+    dc = pr.DeviceCloud(ctx, xo, ro, spans=spans, nodes=nodes)
+    del xo, ro
+    log(f"lod: {n} points, depth {depth}, {len(spans)} batches, ready after {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+    views = {"stereo_2x2016x2240": synth.stereo_cameras(synth.C3_SEED),
+             "orbit_1920x1080": [synth.orbit_camera(7)]}
+    out = {"points": n, "depth": depth, "batches": len(spans), "cap": 10240}
+    for vname, cams in views.items():
+        vbs = [torch.empty(c.width * c.height, dtype=torch.int64, device="cuda") for c in cams]
+        fbs = [torch.empty(c.width * c.height, dtype=torch.int32, device="cuda") for c in cams]
+        res = {}
+        for lod_px in (0.0, 100.0):
+            processed = 0
+            for c, vb in zip(cams, vbs):
+                pr.pr_render(ctx.handle, dc.handle, c.view, c.proj, c.width, c.height,
+                             pr.RenderOpts.make(counters=1, lod_px=lod_px), vb)
+                processed += pr.pr_get_stats(ctx.handle)["points"]
+            o = pr.RenderOpts.make(lod_px=lod_px)
+
+            def step():
+                for c, vb, fb in zip(cams, vbs, fbs):
+                    pr.pr_render(ctx.handle, dc.handle, c.view, c.proj, c.width, c.height, o, vb)
+                    pr.pr_resolve(ctx.handle, dc.handle, vb, c.width, c.height, 0xFF000000, fb)
+
+            for _ in range(warmup):
+                step()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            torch.cuda.synchronize()
+            for a, b in ev:
+                a.record(stream)
+                step()
+                b.record(stream)
+            torch.cuda.synchronize()
+            t = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            res[f"lod_px_{int(lod_px)}"] = {"ms_per_frame": round(t, 4), "processed_points": processed,
+                                            "gpts": round(processed / (t * 1e-3) / 1e9, 3),
+                                            "all_points_rate_gpts": round(n * len(cams) / (t * 1e-3) / 1e9, 3)}
+        res["frame_speedup"] = round(res["lod_px_0"]["ms_per_frame"] / res["lod_px_100"]["ms_per_frame"], 3)
+        out[vname] = res
+        log(f"lod {vname}: {res}")
+    pr.pr_sync(ctx.handle)
+    dc.close()
+    del dc
+    torch.cuda.empty_cache()
+    return out
+
+
 def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
     """Served workload: 8 resident terrain clouds (3.41e9 points), a seeded Poisson request stream with random
     cameras and image sizes 640x480 / 1920x1080 / 3840x2160, admission by visibility + framebuffer bytes.
@@ -335,6 +395,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true", help="skip the served-mode leg")
+    ap.add_argument("--lod-points", type=int, default=500_000_000, help="points of the LOD leg (0: skip)")
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-rate", type=float, default=500.0)
     ap.add_argument("--served-budget", type=int, default=4 << 30, help="bytes of visibility + frame buffers in flight")
@@ -456,6 +517,8 @@ def main():
     pr.pr_cloud_free(cloud["handle"])
     cloud["mem"].clear()
     torch.cuda.empty_cache()
+    if args.lod_points:
+        out["lod"] = lod_leg(pr, ctx, args.lod_points, args.steps, args.warmup)
     if not args.no_served:
         out["served"] = served_leg(pr, ctx, args.served_requests, args.served_rate, args.served_budget)
     if not args.no_cpu:

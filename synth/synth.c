@@ -509,10 +509,14 @@ int synth_terrain(uint64_t seed, uint64_t n, double sigma, int order, float* xyz
  * spans[2b + 1] = count, nodes[5b ..] = cube origin x, y, z, edge, level.
  * Returns 0; -1 bad arguments; -2 no memory; -3 output capacity too small
  * (*npad_out, *nb_out then hold what is needed). */
-static inline uint64_t spread3_20(uint64_t v) {
-  uint64_t r = 0;
-  for (int b = 0; b < 20; ++b) r |= ((v >> b) & 1ull) << (3 * b);
-  return r;
+static inline uint64_t spread3_20(uint64_t v) { /* bit b -> bit 3b, 20 bits */
+  v &= 0xFFFFFull;
+  v = (v | (v << 32)) & 0x1F00000000FFFFull;
+  v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+  v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+  v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
 }
 static inline uint64_t compact3_20(uint64_t c) {
   uint64_t r = 0;
@@ -520,79 +524,160 @@ static inline uint64_t compact3_20(uint64_t c) {
   return r;
 }
 
+typedef struct {
+  const float* xyz;
+  uint64_t seed;
+  int depth;
+  double cdf[16], mn[3], size;
+  uint64_t* key;
+  uint32_t* idx;
+} lpc_keys_job;
+
+static void lpc_keys(void* arg, uint64_t lo, uint64_t hi) {
+  lpc_keys_job* J = (lpc_keys_job*)arg;
+  for (uint64_t i = lo; i < hi; ++i) {
+    double u = u01(sm_at(J->seed ^ 0x4C50434C50434C50ull, i));
+    int L = 0;
+    while (L < J->depth && u >= J->cdf[L]) ++L;
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      double f = floor((((double)J->xyz[3 * i + a] - J->mn[a]) * 1048576.0) / J->size);
+      q[a] = f >= 1048575.0 ? 1048575u : (f <= 0.0 ? 0u : (uint64_t)f);
+    }
+    J->key[i] = ((uint64_t)L << 60) | spread3_20(q[0]) | (spread3_20(q[1]) << 1) | (spread3_20(q[2]) << 2);
+    J->idx[i] = (uint32_t)i;
+  }
+}
+
+/* Stable LSD radix sort of (key, idx) pairs, 8-bit digits, chunk-parallel:
+ * per-chunk digit counts, offsets in (digit, chunk) order, scatter in chunk
+ * order (each chunk keeps its input order). */
+typedef struct {
+  uint64_t *kin, *kout;
+  uint32_t *iin, *iout;
+  uint64_t n;
+  int sh, nt;
+  uint64_t* off; /* nt x 256 */
+} radix_job;
+
+static void radix_count(void* arg, uint64_t c0, uint64_t c1) {
+  radix_job* R = (radix_job*)arg;
+  for (uint64_t c = c0; c < c1; ++c) {
+    uint64_t* h = R->off + 256 * c;
+    memset(h, 0, 256 * sizeof(uint64_t));
+    uint64_t lo = R->n * c / (uint64_t)R->nt, hi = R->n * (c + 1) / (uint64_t)R->nt;
+    for (uint64_t i = lo; i < hi; ++i) h[(R->kin[i] >> R->sh) & 255u]++;
+  }
+}
+static void radix_scatter(void* arg, uint64_t c0, uint64_t c1) {
+  radix_job* R = (radix_job*)arg;
+  for (uint64_t c = c0; c < c1; ++c) {
+    uint64_t* h = R->off + 256 * c;
+    uint64_t lo = R->n * c / (uint64_t)R->nt, hi = R->n * (c + 1) / (uint64_t)R->nt;
+    for (uint64_t i = lo; i < hi; ++i) {
+      uint64_t d = h[(R->kin[i] >> R->sh) & 255u]++;
+      R->kout[d] = R->kin[i];
+      R->iout[d] = R->iin[i];
+    }
+  }
+}
+
+typedef struct {
+  const float* xyz;
+  const uint32_t* rgba;
+  const uint32_t* idx;     /* sorted order */
+  const uint64_t* src;     /* per batch: first sorted position */
+  const uint32_t* spans;
+  float* xyz_out;
+  uint32_t* rgba_out;
+} lpc_gather_job;
+
+static void lpc_gather(void* arg, uint64_t b0, uint64_t b1) {
+  lpc_gather_job* G = (lpc_gather_job*)arg;
+  for (uint64_t b = b0; b < b1; ++b) {
+    uint64_t pos = G->spans[2 * b], cnt = G->spans[2 * b + 1];
+    for (uint64_t t = 0; t < cnt; ++t) {
+      uint64_t s = G->idx[G->src[b] + t], d = pos + t;
+      G->xyz_out[3 * d] = G->xyz[3 * s];
+      G->xyz_out[3 * d + 1] = G->xyz[3 * s + 1];
+      G->xyz_out[3 * d + 2] = G->xyz[3 * s + 2];
+      G->rgba_out[d] = G->rgba[s];
+    }
+  }
+}
+
 int synth_lpc_layout(uint64_t seed, const float* xyz, const uint32_t* rgba, uint64_t n, int depth, uint32_t cap,
                      float* xyz_out, uint32_t* rgba_out, uint64_t cap_points, uint32_t* spans, double* nodes,
                      uint64_t cap_batches, uint64_t* npad_out, uint64_t* nb_out) {
   if (!xyz || !rgba || !npad_out || !nb_out || depth < 0 || depth > 15 || cap < 4 || n >= (1ull << 32)) return -1;
-  double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+  lpc_keys_job J;
+  memset(&J, 0, sizeof J);
+  J.xyz = xyz;
+  J.seed = seed;
+  J.depth = depth;
+  double mx[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) {
-    mn[a] = n ? (double)xyz[a] : 0.0;
-    mx[a] = mn[a];
+    J.mn[a] = n ? (double)xyz[a] : 0.0;
+    mx[a] = J.mn[a];
   }
   for (uint64_t i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) {
       double v = (double)xyz[3 * i + a];
-      if (v < mn[a]) mn[a] = v;
+      if (v < J.mn[a]) J.mn[a] = v;
       if (v > mx[a]) mx[a] = v;
     }
-  double size = 0.0;
+  J.size = 0.0;
   for (int a = 0; a < 3; ++a)
-    if (mx[a] - mn[a] > size) size = mx[a] - mn[a];
-  if (size == 0.0) size = 1.0;
+    if (mx[a] - J.mn[a] > J.size) J.size = mx[a] - J.mn[a];
+  if (J.size == 0.0) J.size = 1.0;
   /* level CDF: P(L <= l) = (4^(l+1) - 1) / (4^(depth+1) - 1) */
-  double cdf[16];
   double tot = 0.0, acc = 0.0;
   for (int l = 0; l <= depth; ++l) tot += ldexp(1.0, 2 * l);
   for (int l = 0; l <= depth; ++l) {
     acc += ldexp(1.0, 2 * l);
-    cdf[l] = acc / tot;
+    J.cdf[l] = acc / tot;
   }
-  uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
-  uint64_t* key2 = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
-  uint32_t* idx = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
-  uint32_t* idx2 = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
-  if (!key || !key2 || !idx || !idx2) {
-    free(key); free(key2); free(idx); free(idx2);
+  int nt = pick_threads(0);
+  uint64_t m = n ? n : 1;
+  uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * m);
+  uint64_t* key2 = (uint64_t*)malloc(sizeof(uint64_t) * m);
+  uint32_t* idx = (uint32_t*)malloc(sizeof(uint32_t) * m);
+  uint32_t* idx2 = (uint32_t*)malloc(sizeof(uint32_t) * m);
+  uint64_t* off = (uint64_t*)malloc(sizeof(uint64_t) * 256 * (uint64_t)nt);
+  if (!key || !key2 || !idx || !idx2 || !off) {
+    free(key); free(key2); free(idx); free(idx2); free(off);
     return -2;
   }
-  for (uint64_t i = 0; i < n; ++i) {
-    double u = u01(sm_at(seed ^ 0x4C50434C50434C50ull, i));
-    int L = 0;
-    while (L < depth && u >= cdf[L]) ++L;
-    uint64_t q[3];
-    for (int a = 0; a < 3; ++a) {
-      double f = floor((((double)xyz[3 * i + a] - mn[a]) * 1048576.0) / size);
-      q[a] = f >= 1048575.0 ? 1048575u : (f <= 0.0 ? 0u : (uint64_t)f);
-    }
-    key[i] = ((uint64_t)L << 60) | spread3_20(q[0]) | (spread3_20(q[1]) << 1) | (spread3_20(q[2]) << 2);
-    idx[i] = (uint32_t)i;
-  }
-  /* stable LSD radix sort of (key, idx), 8 bits per pass */
-  uint64_t* cnt = (uint64_t*)calloc(256, sizeof(uint64_t));
-  if (!cnt) {
-    free(key); free(key2); free(idx); free(idx2);
-    return -2;
-  }
+  J.key = key;
+  J.idx = idx;
+  parallel_for(n, nt, lpc_keys, &J);
+  radix_job R;
+  R.n = n;
+  R.nt = nt;
+  R.off = off;
   for (int pass = 0; pass < 8; ++pass) {
-    int sh = 8 * pass;
-    memset(cnt, 0, 256 * sizeof(uint64_t));
-    for (uint64_t i = 0; i < n; ++i) cnt[(key[i] >> sh) & 255u]++;
+    R.kin = key; R.iin = idx; R.kout = key2; R.iout = idx2; R.sh = 8 * pass;
+    parallel_for((uint64_t)nt, nt, radix_count, &R);
     uint64_t s = 0;
-    for (int d = 0; d < 256; ++d) {
-      uint64_t c = cnt[d];
-      cnt[d] = s;
-      s += c;
-    }
-    for (uint64_t i = 0; i < n; ++i) {
-      uint64_t d = cnt[(key[i] >> sh) & 255u]++;
-      key2[d] = key[i];
-      idx2[d] = idx[i];
-    }
+    for (int d = 0; d < 256; ++d)
+      for (int c = 0; c < nt; ++c) {
+        uint64_t v = off[256 * c + d];
+        off[256 * c + d] = s;
+        s += v;
+      }
+    parallel_for((uint64_t)nt, nt, radix_scatter, &R);
     uint64_t* tk = key; key = key2; key2 = tk;
     uint32_t* ti = idx; idx = idx2; idx2 = ti;
   }
-  free(cnt);
-  /* nodes and batches */
+  free(off);
+  free(key2);
+  free(idx2);
+  /* nodes and batches (a serial walk over the sorted keys) */
+  uint64_t* src = (uint64_t*)malloc(sizeof(uint64_t) * (cap_batches ? cap_batches : 1));
+  if (!src) {
+    free(key); free(idx);
+    return -2;
+  }
   uint64_t pos = 0, nb = 0;
   int fits = 1;
   uint64_t i = 0;
@@ -601,26 +686,20 @@ int synth_lpc_layout(uint64_t seed, const float* xyz, const uint32_t* rgba, uint
     uint64_t cell = (key[i] & ((1ull << 60) - 1)) >> (3 * (20 - L));
     uint64_t j = i;
     while (j < n && (int)(key[j] >> 60) == L && ((key[j] & ((1ull << 60) - 1)) >> (3 * (20 - L))) == cell) ++j;
-    double edge = ldexp(size, -L);
+    double edge = ldexp(J.size, -L);
     for (uint64_t c0 = i; c0 < j; c0 += cap) {
       uint64_t c1 = c0 + cap < j ? c0 + cap : j;
       pos = (pos + 3) & ~3ull;
       if (nb < cap_batches && pos + (c1 - c0) <= cap_points && xyz_out && rgba_out && spans && nodes) {
         spans[2 * nb] = (uint32_t)pos;
         spans[2 * nb + 1] = (uint32_t)(c1 - c0);
+        src[nb] = c0;
         for (int a = 0; a < 3; ++a) {
           uint64_t k = compact3_20(cell << (3 * (20 - L)) >> a) >> (20 - L);
-          nodes[5 * nb + a] = mn[a] + (double)k * edge;
+          nodes[5 * nb + a] = J.mn[a] + (double)k * edge;
         }
         nodes[5 * nb + 3] = edge;
         nodes[5 * nb + 4] = (double)L;
-        for (uint64_t t = c0; t < c1; ++t) {
-          uint64_t s = idx[t], d = pos + (t - c0);
-          xyz_out[3 * d] = xyz[3 * s];
-          xyz_out[3 * d + 1] = xyz[3 * s + 1];
-          xyz_out[3 * d + 2] = xyz[3 * s + 2];
-          rgba_out[d] = rgba[s];
-        }
       } else {
         fits = 0;
       }
@@ -629,7 +708,13 @@ int synth_lpc_layout(uint64_t seed, const float* xyz, const uint32_t* rgba, uint
     }
     i = j;
   }
-  free(key); free(key2); free(idx); free(idx2);
+  if (fits) {
+    lpc_gather_job G = {xyz, rgba, idx, src, spans, xyz_out, rgba_out};
+    parallel_for(nb, nt, lpc_gather, &G);
+  }
+  free(src);
+  free(key);
+  free(idx);
   *npad_out = pos;
   *nb_out = nb;
   return fits ? 0 : -3;
