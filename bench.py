@@ -72,7 +72,7 @@ def load_cloud(ctx, wl, chunk=64_000_000, on_chunk=None):
     import paper_2204_01287_amd as pr
     import synth
 
-    n, S, morton = wl["n"], 10240, wl["morton"]
+    n, S, morton = wl["n"], wl.get("batch_size", 10240), wl["morton"]
     sizes = pr.pr_cloud_sizes(n, S, morton)
     dev = torch.device("cuda", 0)
     mem = {f: torch.empty(max(getattr(sizes, f), 256), dtype=torch.uint8, device=dev) for f in pr.DeviceCloud.FIELDS}
@@ -177,7 +177,7 @@ def kernel_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("kern_render.hip", "internal.h"):
+    for f in ("raster_core.h", "kern_raster.hip", "kern_render.hip", "internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2204_01287_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -325,6 +325,152 @@ def lod_leg(pr, ctx, n: int, steps: int, warmup: int):
     return out
 
 
+def autotune_leg(pr, ctx, cloud, cams, vbs, frame, plain_ms, steps, warmup):
+    """The autotuner on the headline workload: pr_autotune over the stereo pair (workgroup shape, tile bound,
+    grid; the batch size stays 10,240), then the plain step timed again under the winner."""
+    import numpy as np
+    import torch
+
+    need = pr.pr_views_work_bytes(cloud["handle"], len(cams))
+    work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    views = [(c.view, c.proj, c.width, c.height, vb) for c, vb in zip(cams, vbs)]
+    t0 = time.perf_counter()
+    best, trials = pr.pr_autotune(ctx.handle, cloud["handle"], views, None, work, need, 3)
+    t_tune = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        frame()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        frame()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    pr.pr_set_tuning(ctx.handle)
+    shapes = pr.pr_raster_shapes(ctx.handle)
+    default_ms = next(m for t, m in trials if t == {"shape": 0, "tile_px": 0, "wg_per_cu": 0})
+    res = {"candidates": len(trials), "tune_s": round(t_tune, 2), "best": best, "best_shape": shapes[best["shape"]],
+           "multiview_frame_ms": {"default": round(default_ms, 4), "best": round(min(m for _, m in trials), 4)},
+           "plain_step_ms": {"default": round(plain_ms, 4), "tuned": round(ms, 4)},
+           "top5": [{"tuning": t, "shape": shapes[t["shape"]], "ms": round(m, 4)}
+                    for t, m in sorted(trials, key=lambda x: x[1])[:5]]}
+    log(f"autotune (stereo): {res}")
+    return res
+
+
+class _BenchCloud:
+    """A cloud loaded by load_cloud, with the handle/close interface the batch-size tuner expects."""
+
+    def __init__(self, pr, c):
+        self.pr, self.c, self.handle, self.nb = pr, c, c["handle"], c["nb"]
+
+    def close(self):
+        if self.handle:
+            self.pr.pr_cloud_free(self.handle)
+            self.handle = None
+            self.c["mem"].clear()
+
+
+def camera_array_leg(pr, ctx, n: int, steps: int, warmup: int, sizes=(5120, 10240, 20480)):
+    """Camera array: 64 views of 1024x1024 at random cameras over an n-point terrain (seed 4, Morton batches).
+    The autotuner sweeps batch size x workgroup shape x tile bound x grid on the 64-view frame; then 64
+    single-view launches (pr_render + resolve each) against one multi-view launch (+ 64 resolves), under the
+    default configuration (10,240, shape 0) and the tuned one.  Every configuration renders the same images."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2204_01287_amd.autotune import tune
+
+    cams = synth.camera_array(4, 64, 1024, 1024)
+    vbs = [torch.empty(c.width * c.height, dtype=torch.int64, device="cuda") for c in cams]
+    fbs = [torch.empty(c.width * c.height, dtype=torch.int32, device="cuda") for c in cams]
+    stream = torch.cuda.current_stream()
+    kept = {}
+
+    def build(S):
+        c = _BenchCloud(pr, load_cloud(ctx, dict(name=f"terrain_c4_S{S}", seed=4, n=n, morton=True, order=0,
+                                                 batch_size=S)))
+        kept[S] = c
+        return _Keep(c)
+
+    t0 = time.perf_counter()
+    res = tune(ctx, build, sizes, cams, reps=2, log=log)
+    t_tune = time.perf_counter() - t0
+    best = res["best"]
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    out = {"points": n, "views": "64 x 1024x1024", "tune_s": round(t_tune, 1), "candidates": len(res["trials"]),
+           "best": best, "best_shape": pr.pr_raster_shapes(ctx.handle)[best["tuning"]["shape"]]}
+    configs = {"default": (10240, {"shape": 0, "tile_px": 0, "wg_per_cu": 0}),
+               "tuned": (best["batch_size"], best["tuning"])}
+    for name, (S, t) in configs.items():
+        c = kept[S]
+        pr.pr_set_tuning(ctx.handle, **t)
+        processed = 0
+        for cam, vb in zip(cams, vbs):
+            pr.pr_render(ctx.handle, c.handle, cam.view, cam.proj, cam.width, cam.height,
+                         pr.RenderOpts.make(counters=1), vb)
+            processed += pr.pr_get_stats(ctx.handle)["points"]
+        need = pr.pr_views_work_bytes(c.handle, len(cams))
+        work = torch.empty(need, dtype=torch.uint8, device="cuda")
+        vlist = [(cam.view, cam.proj, cam.width, cam.height, vb) for cam, vb in zip(cams, vbs)]
+
+        def plain():
+            for cam, vb, fb in zip(cams, vbs, fbs):
+                pr.pr_render(ctx.handle, c.handle, cam.view, cam.proj, cam.width, cam.height, None, vb)
+                pr.pr_resolve(ctx.handle, c.handle, vb, cam.width, cam.height, 0xFF000000, fb)
+
+        def multi():
+            pr.pr_render_views(ctx.handle, c.handle, vlist, None, work, need)
+            for cam, vb, fb in zip(cams, vbs, fbs):
+                pr.pr_resolve(ctx.handle, c.handle, vb, cam.width, cam.height, 0xFF000000, fb)
+
+        p_ms, m_ms = timed(plain), timed(multi)
+        out[name] = {"batch_size": S, "tuning": t, "processed_points": processed,
+                     "plain_64_launches_ms": round(p_ms, 3), "multiview_one_launch_ms": round(m_ms, 3),
+                     "plain_gpts": round(processed / (p_ms * 1e-3) / 1e9, 2),
+                     "multiview_gpts": round(processed / (m_ms * 1e-3) / 1e9, 2),
+                     "multiview_speedup": round(p_ms / m_ms, 3)}
+        log(f"camera array {name}: {out[name]}")
+        del work
+    out["tuned_vs_default_multiview"] = round(out["default"]["multiview_one_launch_ms"] /
+                                              out["tuned"]["multiview_one_launch_ms"], 3)
+    bys = {}
+    for t in res["trials"]:
+        bys[t["batch_size"]] = min(bys.get(t["batch_size"], 1e30), t["ms"])
+    out["best_ms_by_batch_size"] = {str(k): round(v, 3) for k, v in bys.items()}
+    pr.pr_set_tuning(ctx.handle)
+    pr.pr_sync(ctx.handle)
+    for c in kept.values():
+        c.close()
+    kept.clear()
+    torch.cuda.empty_cache()
+    return out
+
+
+class _Keep:
+    """Hands a cloud to the tuner without letting it free the cloud (the leg times it again afterwards)."""
+
+    def __init__(self, c):
+        self.handle = c.handle
+
+    def close(self):
+        pass
+
+
 def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
     """Served workload: 8 resident terrain clouds (3.41e9 points), a seeded Poisson request stream with random
     cameras and image sizes 640x480 / 1920x1080 / 3840x2160, admission by visibility + framebuffer bytes.
@@ -396,6 +542,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true", help="skip the served-mode leg")
     ap.add_argument("--lod-points", type=int, default=500_000_000, help="points of the LOD leg (0: skip)")
+    ap.add_argument("--array-points", type=int, default=500_000_000,
+                    help="points of the 64-camera array leg with the batch-size autotuner (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner leg on the headline workload")
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-rate", type=float, default=500.0)
     ap.add_argument("--served-budget", type=int, default=4 << 30, help="bytes of visibility + frame buffers in flight")
@@ -514,11 +663,15 @@ def main():
     out["multiview"] = multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, ms_per_step,
                                             args.steps, args.warmup)
     out["hqs"] = hqs_leg(pr, ctx, cloud, cams, processed, args.steps, args.warmup)
+    if not args.no_autotune:
+        out["autotune"] = autotune_leg(pr, ctx, cloud, cams, vbs, frame, ms_per_step, args.steps, args.warmup)
     pr.pr_cloud_free(cloud["handle"])
     cloud["mem"].clear()
     torch.cuda.empty_cache()
     if args.lod_points:
         out["lod"] = lod_leg(pr, ctx, args.lod_points, args.steps, args.warmup)
+    if args.array_points:
+        out["camera_array"] = camera_array_leg(pr, ctx, args.array_points, min(args.steps, 10), min(args.warmup, 2))
     if not args.no_served:
         out["served"] = served_leg(pr, ctx, args.served_requests, args.served_rate, args.served_budget)
     if not args.no_cpu:

@@ -265,6 +265,64 @@ pr_status pr_cloud_drop_load_buffers(pr_cloud* cloud);
 /* Free the host handle only; device buffers stay the caller's. */
 void pr_cloud_free(pr_cloud* cloud);
 
+/* ---- workgroup shapes and autotuning (Sec. 3.2 fixes one workgroup size and
+ * number of points per thread for its GPU and reports a sweep of the latter)
+ *
+ * The library carries several compiled shapes of its persistent render
+ * kernel.  A context renders with one shape and two run-time settings, its
+ * tuning.  Every shape and every tuning gives the same visibility buffers and
+ * counters, bit for bit (the combination is a minimum): they change the speed
+ * only.  The batch size S, the third parameter of the paper's sweep, is fixed
+ * when the cloud is built (pr_build_batches); points per thread follow as
+ * S / (64 * waves). */
+typedef struct {
+  uint32_t waves;         /* waves of 64 lanes per workgroup                     */
+  uint32_t depth;         /* groups of 256 points (4 per lane) in flight per wave */
+  uint32_t tile_px;       /* pixels of the workgroup's LDS tile (8 bytes each)   */
+  uint32_t max_wg_per_cu; /* single-view workgroups that fit on one CU at once   */
+} pr_raster_shape;
+
+typedef struct {
+  uint32_t shape;     /* index into the shapes of pr_raster_shapes [0]                      */
+  uint32_t tile_px;   /* largest batch rectangle combined in LDS, at most the shape's tile;
+                         0 = the shape's tile [0]                                           */
+  uint32_t wg_per_cu; /* persistent workgroups per CU, at most what fits; 0 = all that fit [0] */
+  uint32_t reserved;  /* must be 0                                                          */
+} pr_tuning;
+
+/* The compiled shapes in index order (shape 0 is the default): writes
+ * min(cap, count) records to out (host, may be NULL when cap is 0) and the
+ * count to *count. */
+pr_status pr_raster_shapes(const pr_ctx* ctx, pr_raster_shape* out, uint32_t cap, uint32_t* count);
+
+/* Set the context's tuning (NULL: the default {0, 0, 0, 0}); later frames on
+ * this context use it.  Not for a context with frames being enqueued from
+ * another thread.  PR_EINVAL for an unknown shape, tile_px above the
+ * shape's tile, wg_per_cu above what fits, or reserved != 0. */
+pr_status pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
+pr_status pr_get_tuning(const pr_ctx* ctx, pr_tuning* out);
+
+/* One candidate of pr_autotune and its mean frame time. */
+typedef struct {
+  pr_tuning tuning;
+  float ms;           /* one pr_render_views frame (all views), HIP events on the context's stream */
+  uint32_t reserved;
+} pr_tune_trial;
+
+/* Autotuner: times pr_render_views(ctx, cloud, views, nviews, opts, work,
+ * work_bytes) under each candidate tuning (every shape, its full and half
+ * tile bound, all and half of the workgroups that fit), one untimed frame
+ * then reps timed frames each (reps 0 = 3), and sets the context's tuning to
+ * the fastest (the first of equal times).  The candidates' trials go to
+ * trials (host, first min(cap, total) in candidate order; may be NULL when
+ * cap is 0), their number to *ntrials, the winner to *best (may be NULL).
+ * Afterwards every view's visibility buffer holds the frame.  Synchronises.
+ * opts->accumulate and opts->counters must be 0 (PR_EINVAL); other errors as
+ * pr_render_views.  On an error the context's tuning is left unchanged. */
+pr_status pr_autotune(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                      const pr_render_opts* opts, void* work, uint64_t work_bytes, uint32_t reps,
+                      pr_tune_trial* trials, uint32_t cap, uint32_t* ntrials, pr_tuning* best);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,8 @@ _STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "
 EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_load_points", "pr_build_batches",
             "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
             "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers", "pr_render_hqs",
-            "pr_cloud_sizes_spans", "pr_build_batches_spans"]
+            "pr_cloud_sizes_spans", "pr_build_batches_spans", "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning",
+            "pr_autotune"]
 
 
 class PrError(RuntimeError):
@@ -66,6 +67,26 @@ class View(ctypes.Structure):
                 ("h", ctypes.c_uint32), ("visbuf", ctypes.c_void_p)]
 
 
+class RasterShape(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_uint32), ("depth", ctypes.c_uint32), ("tile_px", ctypes.c_uint32),
+                ("max_wg_per_cu", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_uint32), ("tile_px", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {"shape": self.shape, "tile_px": self.tile_px, "wg_per_cu": self.wg_per_cu}
+
+
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("tuning", Tuning), ("ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("culled", ctypes.c_uint64), ("points", ctypes.c_uint64),
                 ("level_batches", ctypes.c_uint64 * 3), ("level_points", ctypes.c_uint64 * 3),
@@ -97,12 +118,18 @@ lib.pr_build_batches_spans.argtypes = [_P, _P, _P, _P, _U64]
 lib.pr_render_hqs.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts), ctypes.c_float, _P, _P, _U32, _P]
 lib.pr_render_views.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64]
 lib.pr_sync.argtypes = [_P]
+lib.pr_raster_shapes.argtypes = [_P, ctypes.POINTER(RasterShape), _U32, ctypes.POINTER(_U32)]
+lib.pr_set_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+lib.pr_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+lib.pr_autotune.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64, _U32,
+                            ctypes.POINTER(TuneTrial), _U32, ctypes.POINTER(_U32), ctypes.POINTER(Tuning)]
 lib.pr_cloud_info.argtypes = [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U32)]
 lib.pr_cloud_free.argtypes = [_P]
 lib.pr_cloud_free.restype = None
 for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
            "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views",
-           "pr_cloud_drop_load_buffers", "pr_render_hqs", "pr_cloud_sizes_spans", "pr_build_batches_spans"):
+           "pr_cloud_drop_load_buffers", "pr_render_hqs", "pr_cloud_sizes_spans", "pr_build_batches_spans",
+           "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning", "pr_autotune"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -210,15 +237,53 @@ def pr_views_work_bytes(cloud, nviews: int) -> int:
     return out.value
 
 
-def pr_render_views(ctx, cloud, views, opts: RenderOpts | None, work, work_bytes: int):
-    """views: sequence of (view, proj, w, h, visbuf); work: device buffer of pr_views_work_bytes bytes."""
+def _views(views):
     arr = (View * len(views))()
     for i, (v, p, w, h, vb) in enumerate(views):
         arr[i].view[:] = [float(x) for x in np.asarray(v, dtype=np.float32).reshape(16)]
         arr[i].proj[:] = [float(x) for x in np.asarray(p, dtype=np.float32).reshape(16)]
         arr[i].w, arr[i].h, arr[i].visbuf = w, h, _ptr(vb)
-    _check(lib.pr_render_views(ctx, cloud, arr, len(views), ctypes.byref(opts) if opts is not None else None,
-                               _ptr(work), work_bytes), "pr_render_views")
+    return arr
+
+
+def pr_render_views(ctx, cloud, views, opts: RenderOpts | None, work, work_bytes: int):
+    """views: sequence of (view, proj, w, h, visbuf); work: device buffer of pr_views_work_bytes bytes."""
+    _check(lib.pr_render_views(ctx, cloud, _views(views), len(views),
+                               ctypes.byref(opts) if opts is not None else None, _ptr(work), work_bytes),
+           "pr_render_views")
+
+
+def pr_raster_shapes(ctx) -> list:
+    """The compiled workgroup shapes, as dicts (waves, depth, tile_px, max_wg_per_cu); index 0 is the default."""
+    n = _U32()
+    _check(lib.pr_raster_shapes(ctx, None, 0, ctypes.byref(n)), "pr_raster_shapes")
+    arr = (RasterShape * n.value)()
+    _check(lib.pr_raster_shapes(ctx, arr, n.value, ctypes.byref(n)), "pr_raster_shapes")
+    return [a.as_dict() for a in arr]
+
+
+def pr_set_tuning(ctx, shape: int = 0, tile_px: int = 0, wg_per_cu: int = 0, reserved: int = 0):
+    t = Tuning(shape, tile_px, wg_per_cu, reserved)
+    _check(lib.pr_set_tuning(ctx, ctypes.byref(t)), "pr_set_tuning")
+
+
+def pr_get_tuning(ctx) -> dict:
+    t = Tuning()
+    _check(lib.pr_get_tuning(ctx, ctypes.byref(t)), "pr_get_tuning")
+    return t.as_dict()
+
+
+def pr_autotune(ctx, cloud, views, opts: RenderOpts | None, work, work_bytes: int, reps: int = 3):
+    """Times every candidate tuning on pr_render_views(views) and keeps the fastest on ctx.
+    Returns (best tuning dict, [(tuning dict, ms), ...] in candidate order)."""
+    arr = _views(views)
+    n = _U32()
+    cap = 256
+    trials = (TuneTrial * cap)()
+    best = Tuning()
+    _check(lib.pr_autotune(ctx, cloud, arr, len(views), ctypes.byref(opts) if opts is not None else None, _ptr(work),
+                           work_bytes, reps, trials, cap, ctypes.byref(n), ctypes.byref(best)), "pr_autotune")
+    return best.as_dict(), [(trials[i].tuning.as_dict(), float(trials[i].ms)) for i in range(min(n.value, cap))]
 
 
 def pr_render_hqs(ctx, cloud, view, proj, w: int, h: int, opts: RenderOpts | None, window: float, visbuf, accum,

@@ -67,6 +67,7 @@ struct RenderArgs {
   int32_t precision, cull, counters;
   float t10, t20;
   uint32_t grid;    // persistent render workgroups
+  uint32_t tile_max;     // classify: largest rectangle (pixels) a tiled batch may cover
   const LodNode* nodes;  // LOD layouts: node per batch (else nullptr)
   float lod_px;          // > 0: cull nodes below the root whose cube projects below lod_px pixels
   // high-quality shading pass only
@@ -105,6 +106,7 @@ struct ClassifyViewsArgs {
   float t10, t20;
   const LodNode* nodes;
   float lod_px;
+  uint32_t tile_max;
   ViewIn v[VIEW_CHUNK];
 };
 struct RenderViewsArgs {
@@ -132,14 +134,36 @@ inline uint64_t views_work_bytes(uint64_t nb, uint32_t nviews) {
 
 // ---- render path (kern_render.hip)
 hipError_t launch_clear(uint64_t* vb, uint64_t npix, DevBlock* dev, FrameHeader* hdr, int reset_stats, hipStream_t s);
-// classify (cull, level, fold, compaction) followed by the persistent render kernel
-hipError_t launch_render(const RenderArgs& a, hipStream_t s);
-uint32_t render_grid(int device);
-// several views: clear, classify per chunk of VIEW_CHUNK views, one persistent render launch
+// classify: cull, level, fold, compaction into the live list (a.tile_max bounds the tiles)
+hipError_t launch_classify(const RenderArgs& a, hipStream_t s);
+// several views: clear, classify per chunk of VIEW_CHUNK views, then one persistent render launch
 hipError_t launch_clear_views(const ClearViewsArgs& a, hipStream_t s);
 hipError_t launch_classify_views(const ClassifyViewsArgs& a, int counters, hipStream_t s);
-hipError_t launch_render_views(const RenderViewsArgs& a, uint64_t max_runs, int counters, hipStream_t s);
-uint32_t render_views_grid(int device);
+
+// ---- persistent render kernels, one compiled workgroup shape each (kern_raster.hip)
+// Every shape computes the same result; they differ in speed only.  The
+// classify launch before a render must bound its tiles by the shape's tile.
+struct RasterShape {
+  uint32_t waves;  // waves of 64 lanes per workgroup
+  uint32_t depth;  // groups of 256 points in flight per wave
+  uint32_t tile;   // pixels of the LDS tile
+  // the live list of the last launch_classify (a.grid workgroups at most)
+  hipError_t (*render)(const RenderArgs& a, hipStream_t s);
+  // the runs of the last classify_views launches
+  hipError_t (*render_views)(const RenderViewsArgs& a, uint64_t max_runs, int counters, hipStream_t s);
+  // workgroups per CU that fit at once (views = 0: single-view kernel, 1: multi-view kernel)
+  int (*per_cu)(int views);
+};
+// The compiled shapes: X(waves, depth, tile).  The first is the default.
+#define PR_RASTER_SHAPES(X)                                                                                  \
+  X(4, 5, 4096) X(4, 3, 4096) X(4, 4, 4096) X(4, 6, 4096) X(4, 5, 2048) X(2, 5, 2048) X(2, 5, 4096)        \
+  X(8, 5, 8192) X(1, 5, 1024)
+#define PR_SHAPE_NAME_(W_, D_, T_) raster_shape_w##W_##_d##D_##_t##T_
+#define PR_SHAPE_NAME(W_, D_, T_) PR_SHAPE_NAME_(W_, D_, T_)
+#define PR_DECLARE_SHAPE(W_, D_, T_) const RasterShape* PR_SHAPE_NAME_(W_, D_, T_)();
+PR_RASTER_SHAPES(PR_DECLARE_SHAPE)
+#undef PR_DECLARE_SHAPE
+
 hipError_t launch_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint64_t ncolors,
                           uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
 // high-quality shading: zero the sums, the shading pass over the live batches of

@@ -18,13 +18,25 @@
 static_assert(sizeof(pr_lod_node) == sizeof(ptr::LodNode), "LOD node layout");
 static_assert(sizeof(pr_batch) == sizeof(ptr::BatchRec), "batch record layout");
 
+namespace {
+// The compiled workgroup shapes of the persistent render kernels; index 0 is the default.
+const ptr::RasterShape* (*const kShapeOf[])() = {
+#define PR_SHAPE_REF(W_, D_, T_) &ptr::PR_SHAPE_NAME_(W_, D_, T_),
+    PR_RASTER_SHAPES(PR_SHAPE_REF)
+#undef PR_SHAPE_REF
+};
+constexpr uint32_t kNumShapes = sizeof(kShapeOf) / sizeof(kShapeOf[0]);
+const ptr::RasterShape& shape_at(uint32_t i) { return *kShapeOf[i](); }
+}  // namespace
+
 struct pr_ctx {
   int device;
   hipStream_t stream;
   ptr::DevBlock* dev;  // counters and flags (device memory)
-  uint32_t render_grid;        // persistent render workgroups that fit on the device at once
-  uint32_t render_views_grid;  // the same for the multi-view render kernel
-  uint32_t accum_grid;         // and for the shading pass
+  uint32_t cus;                     // compute units of the device
+  uint32_t per_cu[kNumShapes][2];   // workgroups per CU that fit at once: single-view, multi-view kernel
+  uint32_t accum_grid;              // persistent workgroups of the shading pass
+  pr_tuning tuning;                 // render shape, tile bound and grid of this context's frames
 };
 
 struct pr_cloud {
@@ -34,8 +46,8 @@ struct pr_cloud {
   uint32_t batch_size;
   int morton;
   int built;
-  int load_dropped;
-  int lod;           // built from spans with LOD nodes  // xyz, rgba, perm and scratch released by the caller: pr_render_views / pr_resolve only
+  int load_dropped;  // xyz, rgba, perm and scratch released by the caller: pr_render_views / pr_resolve only
+  int lod;           // built from spans with LOD nodes
   pr_cloud_bufs bufs;
 };
 
@@ -80,6 +92,20 @@ pr_status check_dims(uint32_t w, uint32_t h) {
 pr_status set_device(const pr_ctx* ctx) {
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   return PR_OK;
+}
+
+// A frame reads the context's tuning once: its render shape, the tile bound of
+// its classify launches (never more than the shape's LDS tile) and its
+// persistent grid.
+const ptr::RasterShape& shape_of(const pr_tuning& t) { return shape_at(t.shape); }
+uint32_t shape_tile(const pr_tuning& t) {
+  const uint32_t full = shape_of(t).tile;
+  return t.tile_px && t.tile_px < full ? t.tile_px : full;
+}
+uint32_t shape_grid(const pr_ctx* ctx, const pr_tuning& t, int views) {
+  uint32_t per = ctx->per_cu[t.shape][views];
+  if (t.wg_per_cu && t.wg_per_cu < per) per = t.wg_per_cu;
+  return per * ctx->cus;
 }
 
 // Pixel-space matrix (Sec. 3.2 projection; the paper leaves toPixelID open):
@@ -155,9 +181,13 @@ pr_status pr_create(int device, void* hip_stream, pr_ctx** out) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->dev = nullptr;
-  c->render_grid = ptr::render_grid(device);
-  c->render_views_grid = ptr::render_views_grid(device);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  c->cus = (uint32_t)cus;
+  for (uint32_t i = 0; i < kNumShapes; ++i)
+    for (int v = 0; v < 2; ++v) c->per_cu[i][v] = (uint32_t)shape_at(i).per_cu(v);
   c->accum_grid = ptr::accum_grid(device);
+  c->tuning = {0, 0, 0, 0};
   e = hipMalloc(reinterpret_cast<void**>(&c->dev), 4096);
   if (e != hipSuccess) {
     delete c;
@@ -398,7 +428,9 @@ pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16],
   a.batches = static_cast<const ptr::BatchRec*>(cloud->bufs.batches);
   a.hdr = hdr;
   a.live = reinterpret_cast<ptr::LiveBatch*>(hdr + 1);
-  a.grid = ctx->render_grid;
+  const pr_tuning tune = ctx->tuning;
+  a.grid = shape_grid(ctx, tune, 0);
+  a.tile_max = shape_tile(tune);
   a.vb = visbuf;
   a.stats = ctx->dev->stats;
   frame_matrix(view, proj, w, h, a.Pm);
@@ -412,7 +444,8 @@ pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16],
   a.t20 = o.t20;
   a.nodes = cloud->lod ? static_cast<const ptr::LodNode*>(cloud->bufs.nodes) : nullptr;
   a.lod_px = o.lod_px;
-  HIP_TRY(ptr::launch_render(a, ctx->stream), "render");
+  HIP_TRY(ptr::launch_classify(a, ctx->stream), "classify");
+  HIP_TRY(shape_of(tune).render(a, ctx->stream), "render");
   return PR_OK;
 }
 
@@ -491,6 +524,7 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
         return fail(PR_ENONFINITE, "pr_render_views: non-finite matrix in view %u", v);
   }
   if (pr_status s = set_device(ctx)) return s;
+  const pr_tuning tune = ctx->tuning;
   const uint64_t nb = cloud->nb;
   const uint32_t nchunks = (nviews + ptr::VIEW_CHUNK - 1) / ptr::VIEW_CHUNK;
   ptr::FrameHeader* hdr = static_cast<ptr::FrameHeader*>(work);
@@ -525,6 +559,7 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
     k.t20 = o.t20;
     k.nodes = cloud->lod ? static_cast<const ptr::LodNode*>(cloud->bufs.nodes) : nullptr;
     k.lod_px = o.lod_px;
+    k.tile_max = shape_tile(tune);
     for (uint32_t v = 0; v < k.nchunk; ++v) {
       const pr_view& pv = views[k.view0 + v];
       frame_matrix(pv.view, pv.proj, pv.w, pv.h, k.v[v].Pm);
@@ -544,9 +579,9 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
   r.hdr = hdr;
   r.stats = ctx->dev->stats;
   r.nviews = nviews;
-  r.grid = ctx->render_views_grid;
+  r.grid = shape_grid(ctx, tune, 1);
   for (uint32_t v = 0; v < nviews; ++v) r.v[v] = {views[v].visbuf, views[v].w, views[v].h};
-  HIP_TRY(ptr::launch_render_views(r, nb * nchunks, o.counters ? 1 : 0, ctx->stream), "render views");
+  HIP_TRY(shape_of(tune).render_views(r, nb * nchunks, o.counters ? 1 : 0, ctx->stream), "render views");
   return PR_OK;
 }
 
@@ -608,5 +643,89 @@ pr_status pr_cloud_info(const pr_cloud* cloud, uint64_t* n, uint64_t* nbatches, 
 }
 
 void pr_cloud_free(pr_cloud* cloud) { delete cloud; }
+
+pr_status pr_raster_shapes(const pr_ctx* ctx, pr_raster_shape* out, uint32_t cap, uint32_t* count) {
+  if (!ctx || !count || (cap && !out)) return fail(PR_EINVAL, "pr_raster_shapes: NULL argument");
+  for (uint32_t i = 0; i < kNumShapes && i < cap; ++i)
+    out[i] = {shape_at(i).waves, shape_at(i).depth, shape_at(i).tile, ctx->per_cu[i][0]};
+  *count = kNumShapes;
+  return PR_OK;
+}
+
+pr_status pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning) {
+  if (!ctx) return fail(PR_EINVAL, "pr_set_tuning: NULL context");
+  const pr_tuning t = tuning ? *tuning : pr_tuning{0, 0, 0, 0};
+  if (t.shape >= kNumShapes) return fail(PR_EINVAL, "pr_set_tuning: shape %u not in 0..%u", t.shape, kNumShapes - 1);
+  if (t.tile_px > shape_at(t.shape).tile)
+    return fail(PR_EINVAL, "pr_set_tuning: tile_px %u above the shape's tile of %u", t.tile_px, shape_at(t.shape).tile);
+  const uint32_t fit = ctx->per_cu[t.shape][0] > ctx->per_cu[t.shape][1] ? ctx->per_cu[t.shape][0]
+                                                                          : ctx->per_cu[t.shape][1];
+  if (t.wg_per_cu > fit) return fail(PR_EINVAL, "pr_set_tuning: wg_per_cu %u above the %u that fit", t.wg_per_cu, fit);
+  if (t.reserved) return fail(PR_EINVAL, "pr_set_tuning: reserved must be 0");
+  ctx->tuning = t;
+  return PR_OK;
+}
+
+pr_status pr_get_tuning(const pr_ctx* ctx, pr_tuning* out) {
+  if (!ctx || !out) return fail(PR_EINVAL, "pr_get_tuning: NULL argument");
+  *out = ctx->tuning;
+  return PR_OK;
+}
+
+pr_status pr_autotune(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                      const pr_render_opts* opts, void* work, uint64_t work_bytes, uint32_t reps,
+                      pr_tune_trial* trials, uint32_t cap, uint32_t* ntrials, pr_tuning* best) {
+  if (!ctx || !ntrials || (cap && !trials)) return fail(PR_EINVAL, "pr_autotune: NULL argument");
+  if (opts && (opts->accumulate || opts->counters))
+    return fail(PR_EINVAL, "pr_autotune: accumulate and counters must be 0");
+  if (pr_status s = set_device(ctx)) return s;
+  if (reps == 0) reps = 3;
+  std::vector<pr_tuning> cand;
+  for (uint32_t i = 0; i < kNumShapes; ++i) {
+    const uint32_t fit = ctx->per_cu[i][1];
+    for (uint32_t tile : {0u, shape_at(i).tile / 2})
+      for (uint32_t wg : {0u, fit / 2})
+        if (wg == 0 || wg < fit) cand.push_back({i, tile, wg, 0});
+  }
+  const pr_tuning saved = ctx->tuning;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  pr_status st = PR_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(PR_EDEVICE, "pr_autotune: events");
+  float best_ms = 0.0f;
+  pr_tuning win = saved;
+  for (size_t c = 0; c < cand.size() && st == PR_OK; ++c) {
+    ctx->tuning = cand[c];
+    st = pr_render_views(ctx, cloud, views, nviews, opts, work, work_bytes);  // untimed: caches, clocks
+    hipError_t e = hipSuccess;
+    if (st == PR_OK) e = hipEventRecord(e0, ctx->stream);
+    for (uint32_t r = 0; r < reps && st == PR_OK && e == hipSuccess; ++r)
+      st = pr_render_views(ctx, cloud, views, nviews, opts, work, work_bytes);
+    if (st != PR_OK) break;
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "pr_autotune: timing");
+      break;
+    }
+    ms /= (float)reps;
+    if (c < cap) trials[c] = {cand[c], ms, 0};
+    if (c == 0 || ms < best_ms) {
+      best_ms = ms;
+      win = cand[c];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != PR_OK) {
+    ctx->tuning = saved;
+    return st;
+  }
+  ctx->tuning = win;
+  *ntrials = (uint32_t)cand.size();
+  if (best) *best = win;
+  return PR_OK;
+}
 
 }  // extern "C"

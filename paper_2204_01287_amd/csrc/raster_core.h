@@ -1,0 +1,515 @@
+// Point-raster core shared by every render-path translation unit: decode,
+// projection, exact floor, the per-point loops of the visibility pass and of
+// the shading pass, and the persistent render kernels.
+//
+// The workgroup shape is fixed per translation unit by three macros, so that
+// the library can carry several compiled shapes of the same kernels and pick
+// one at run time (every shape computes the same result):
+//   PR_WAVES  waves per workgroup (64 lanes each)                  [4]
+//   PR_DEPTH  groups of 256 points in flight per wave (prefetch)   [5]
+//   PR_TILE   pixels of the workgroup's LDS tile (8 bytes each)    [4096]
+#ifndef PR_RASTER_CORE_H
+#define PR_RASTER_CORE_H
+
+#include "internal.h"
+
+#ifndef PR_WAVES
+#define PR_WAVES 4
+#endif
+#ifndef PR_DEPTH
+#define PR_DEPTH 5
+#endif
+#ifndef PR_TILE
+#define PR_TILE 4096
+#endif
+
+namespace ptr {
+namespace {
+
+constexpr int CLS_INSIDE = 0, CLS_PARTIAL = 1, CLS_SLOW = 2;
+constexpr int WAVES = PR_WAVES;
+constexpr int THREADS = 64 * WAVES;
+constexpr uint32_t TILE_MAX = PR_TILE;  // LDS tile of 64-bit keys
+constexpr int PREFETCH = PR_DEPTH;      // groups of 256 points in flight per wave
+static_assert(WAVES >= 1 && WAVES <= 16 && PREFETCH >= 1 && PREFETCH <= 8, "workgroup shape");
+static_assert(TILE_MAX >= 256 && TILE_MAX % (2 * 64) == 0 && TILE_MAX * 8 <= 65536, "LDS tile");
+
+// ------------------------------------------------------------------ render
+template <int K>
+__device__ __forceinline__ void decode(uint32_t lw, uint32_t mw, uint32_t hw, float& X, float& Y, float& Z) {
+  if constexpr (K == 10) {
+    X = (float)(lw & 1023u);
+    Y = (float)((lw >> 10) & 1023u);
+    Z = (float)((lw >> 20) & 1023u);
+  } else if constexpr (K == 20) {
+    X = (float)(((lw & 1023u) << 10) | (mw & 1023u));
+    Y = (float)((((lw >> 10) & 1023u) << 10) | ((mw >> 10) & 1023u));
+    Z = (float)((((lw >> 20) & 1023u) << 10) | ((mw >> 20) & 1023u));
+  } else {
+    X = (float)(((lw & 1023u) << 20) | ((mw & 1023u) << 10) | (hw & 1023u));
+    Y = (float)((((lw >> 10) & 1023u) << 20) | (((mw >> 10) & 1023u) << 10) | ((hw >> 10) & 1023u));
+    Z = (float)((((lw >> 20) & 1023u) << 20) | (((mw >> 20) & 1023u) << 10) | ((hw >> 20) & 1023u));
+  }
+}
+
+// Frame-wide and batch-wide values of the point loop (uniform: SGPRs).
+struct Loop {
+  float P[3][3], t[3];
+  uint32_t W, H;
+  uint32_t cx, cy;  // 0x4B000000 + tile origin (x0, y0), in VGPRs: pixel_fast yields tile coordinates
+  uint32_t tw, th;  // tile rectangle size (tiled batches)
+  uint32_t tw8;     // tile row pitch in bytes
+  uint64_t* vb;
+  // high-quality shading pass only
+  float window;     // depth window factor
+  uint64_t* acc;    // global sums, two words per pixel
+  float* thr;       // LDS tile of thresholds fl32(closest depth * window)
+};
+
+// Projection of one decoded point (the three fmaf chains, fixed order).
+struct Proj {
+  float hx, hy, hw;
+};
+__device__ __forceinline__ Proj project(const Loop& L, float X, float Y, float Z) {
+  Proj p;
+  p.hx = __builtin_fmaf(L.P[0][2], Z, __builtin_fmaf(L.P[0][1], Y, __builtin_fmaf(L.P[0][0], X, L.t[0])));
+  p.hy = __builtin_fmaf(L.P[1][2], Z, __builtin_fmaf(L.P[1][1], Y, __builtin_fmaf(L.P[1][0], X, L.t[1])));
+  p.hw = __builtin_fmaf(L.P[2][2], Z, __builtin_fmaf(L.P[2][1], Y, __builtin_fmaf(L.P[2][0], X, L.t[2])));
+  return p;
+}
+
+// hw > 0, 0 <= hx < W hw, 0 <= hy < H hw, exactly: the fma residuals carry the
+// exact sign of hx - W hw (denormals are kept, so nothing underflows to 0).
+__device__ __forceinline__ bool visible(const Loop& L, const Proj& p) {
+  return (p.hw > 0.0f) & (p.hx >= 0.0f) & (__builtin_fmaf(-(float)L.W, p.hw, p.hx) < 0.0f) & (p.hy >= 0.0f) &
+         (__builtin_fmaf(-(float)L.H, p.hw, p.hy) < 0.0f);
+}
+
+// floor(hx / hw) - x0 and floor(hy / hw) - y0 for quotients in [0, 2^13), hw
+// in [2^-60, 2^60]: fma(hx, rcp(hw), 2^23) rounds the exact product to an
+// integer n (the spacing of floats in [2^23, 2^24) is 1) with
+// |n - hx/hw| < 1/2 + 2^-9; the exactly signed residual hx - n hw picks n or
+// n - 1.  The integer is read from the float's bits (cx = 0x4B000000 + x0),
+// the correction is the borrow of the same subtraction.
+__device__ __forceinline__ void pixel_fast(const Proj& p, uint32_t cx, uint32_t cy, uint32_t& px, uint32_t& py) {
+  const float r = __builtin_amdgcn_rcpf(p.hw);
+  const float tx = __builtin_fmaf(p.hx, r, 0x1p23f);
+  const float ty = __builtin_fmaf(p.hy, r, 0x1p23f);
+  const float ex = __builtin_fmaf(-(tx - 0x1p23f), p.hw, p.hx);
+  const float ey = __builtin_fmaf(-(ty - 0x1p23f), p.hw, p.hy);
+  unsigned int bo;
+  px = __builtin_subc(__float_as_uint(tx), cx, (unsigned int)(ex < 0.0f), &bo);
+  py = __builtin_subc(__float_as_uint(ty), cy, (unsigned int)(ey < 0.0f), &bo);
+}
+
+// Exact floor of the real quotient for any class: the binary64 quotient of two
+// binary32 values below 2^13 never crosses an integer.
+__device__ __forceinline__ void pixel_exact(const Proj& p, uint32_t& px, uint32_t& py) {
+  px = (uint32_t)floor((double)p.hx / (double)p.hw);
+  py = (uint32_t)floor((double)p.hy / (double)p.hw);
+}
+
+__device__ __forceinline__ uint64_t make_key(float hw, uint32_t idx) {
+  return ((uint64_t)__float_as_uint(hw) << 32) | (uint64_t)idx;
+}
+
+struct Words {
+  uint4 l, m, h;
+  uint4 c;  // colours (shading pass)
+};
+
+// Shading sums of one colour: R + G << 32 and B + 1 << 32 (four 32-bit fields
+// in two 64-bit words, Sec. 3.6).
+__device__ __forceinline__ uint64_t sum_rg(uint32_t c) {
+  return (uint64_t)(c & 255u) | ((uint64_t)((c >> 8) & 255u) << 32);
+}
+__device__ __forceinline__ uint64_t sum_bn(uint32_t c) { return (uint64_t)((c >> 16) & 255u) | (1ull << 32); }
+
+// Shading pass, four consecutive points of one lane: a drawn point joins its
+// pixel's sums iff hw <= fl32(closest depth * window).  Tiled batches add into
+// the LDS sums (tile) behind the LDS threshold tile; others read the closest
+// depth from the visibility buffer and add into the global sums.
+template <int K, int CLS, bool TILED>
+__device__ __forceinline__ void four_points_acc(const Loop& L, uint64_t* tile, const Words& w, uint32_t nvalid) {
+  const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
+  const uint32_t Mw[4] = {w.m.x, w.m.y, w.m.z, w.m.w};
+  const uint32_t Hw[4] = {w.h.x, w.h.y, w.h.z, w.h.w};
+  const uint32_t Cw[4] = {w.c.x, w.c.y, w.c.z, w.c.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float X, Y, Z;
+    decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
+    const Proj p = project(L, X, Y, Z);
+    bool ok = (uint32_t)j < nvalid;
+    if constexpr (CLS != CLS_INSIDE) ok = ok && visible(L, p);
+    uint32_t px, py;
+    if constexpr (CLS == CLS_SLOW)
+      pixel_exact(p, px, py);
+    else
+      pixel_fast(p, L.cx, L.cy, px, py);
+    if constexpr (TILED) {
+      const uint32_t e = __umul24(py, L.tw) + px;
+      if (ok && p.hw <= L.thr[e]) {
+        __hip_atomic_fetch_add(&tile[2 * e], sum_rg(Cw[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&tile[2 * e + 1], sum_bn(Cw[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    } else {
+      ok = ok && (px < L.W) && (py < L.H);
+      const uint32_t off = __umul24(py, L.W) + px;
+      if (ok) {
+        const uint64_t k = __hip_atomic_load(L.vb + off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p.hw <= __uint_as_float((uint32_t)(k >> 32)) * L.window) {
+          __hip_atomic_fetch_add(L.acc + 2 * (uint64_t)off, sum_rg(Cw[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(L.acc + 2 * (uint64_t)off + 1, sum_bn(Cw[j]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+  }
+}
+
+// Four consecutive points of one lane.
+template <int K, int CLS, bool TILED, bool ACC = false>
+__device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const Words& w, uint32_t i0,
+                                            uint32_t nvalid, uint32_t& natom) {
+  if constexpr (ACC) {
+    four_points_acc<K, CLS, TILED>(L, tile, w, nvalid);
+    return;
+  }
+  const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
+  const uint32_t Mw[4] = {w.m.x, w.m.y, w.m.z, w.m.w};
+  const uint32_t Hw[4] = {w.h.x, w.h.y, w.h.z, w.h.w};
+  if constexpr (TILED) {
+    // Tile coordinates straight from the pixel computation.  The classify
+    // kernel tiles a batch only when it has proved that the pixel of every
+    // point of the batch box lies inside the tile rectangle.
+    // Early depth in LDS: the tile entry is read first and the 64-bit LDS
+    // atomic is issued only by a key that beats it (a stale read only costs
+    // an extra atomic: entries never increase).  Most points of a densely
+    // covered pixel lose this test, which removes most of the atomics and
+    // their same-address serialisation.
+    uint8_t* const tb = reinterpret_cast<uint8_t*>(tile);
+    uint32_t ad[4];
+    uint64_t key[4], old[4];
+    bool ok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float X, Y, Z;
+      decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
+      const Proj p = project(L, X, Y, Z);
+      ok[j] = (uint32_t)j < nvalid;
+      if constexpr (CLS != CLS_INSIDE) ok[j] = ok[j] && visible(L, p);
+      uint32_t lx, ly;
+      pixel_fast(p, L.cx, L.cy, lx, ly);
+      key[j] = make_key(p.hw, i0 + j);
+      ad[j] = __umul24(ly, L.tw8) + (lx << 3);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (CLS == CLS_INSIDE) {
+        // Every point of an INSIDE batch box (padding lanes decode to points
+        // of the box too) maps into the tile: the read needs no guard.
+        old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        old[j] = 0;
+        if (ok[j])
+          old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (ok[j] && key[j] < old[j])
+        __hip_atomic_fetch_min(reinterpret_cast<uint64_t*>(tb + ad[j]), key[j], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    uint32_t off[4];
+    uint64_t key[4], old[4];
+    bool ok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float X, Y, Z;
+      decode<K>(Lw[j], Mw[j], Hw[j], X, Y, Z);
+      const Proj p = project(L, X, Y, Z);
+      ok[j] = (uint32_t)j < nvalid;
+      if constexpr (CLS != CLS_INSIDE) ok[j] = ok[j] && visible(L, p);
+      uint32_t px, py;
+      if constexpr (CLS == CLS_SLOW)
+        pixel_exact(p, px, py);
+      else
+        pixel_fast(p, L.cx, L.cy, px, py);
+      // Never address outside the image, whatever the class proofs say.
+      ok[j] = ok[j] && (px < L.W) && (py < L.H);
+      off[j] = __umul24(py, L.W) + px;
+      key[j] = make_key(p.hw, i0 + j);
+    }
+    // all early-depth reads first, then the atomics
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      old[j] = 0;
+      if (ok[j]) old[j] = __hip_atomic_load(L.vb + off[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (ok[j] && key[j] < old[j]) {
+        __hip_atomic_fetch_min(L.vb + off[j], key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        natom++;
+      }
+    }
+  }
+}
+
+// The coordinate streams of the cloud (low, medium, high words).
+struct Streams {
+  const uint32_t* low;
+  const uint32_t* med;
+  const uint32_t* high;
+  const uint32_t* colors;  // shading pass only
+};
+
+template <int K, bool ACC = false>
+__device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, uint32_t g, uint32_t lane) {
+  const uint32_t q = first / 4 + g * 64 + lane;  // first is a multiple of 4
+  Words w;
+  w.l = reinterpret_cast<const uint4*>(a.low)[q];
+  if constexpr (K >= 20) w.m = reinterpret_cast<const uint4*>(a.med)[q];
+  else w.m = make_uint4(0, 0, 0, 0);
+  if constexpr (K == 30) w.h = reinterpret_cast<const uint4*>(a.high)[q];
+  else w.h = make_uint4(0, 0, 0, 0);
+  if constexpr (ACC) w.c = reinterpret_cast<const uint4*>(a.colors)[q];
+  else w.c = make_uint4(0, 0, 0, 0);
+  return w;
+}
+
+// The points of one batch, split over the workgroup's waves: wave w takes the
+// groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
+// 16-byte load per word).  Wave 0 also takes the ragged tail.
+template <int K, int CLS, bool TILED, bool ACC = false>
+__device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
+                              uint32_t wave, uint32_t lane, uint32_t& natom) {
+  const uint32_t ngrp = count >> 8;
+  const uint32_t nj = wave < ngrp ? (ngrp - wave + WAVES - 1) / WAVES : 0;  // this wave's groups
+  if (nj > 0) {
+    // PREFETCH register sets rotate through the wave's groups; each is
+    // reloaded in place right after use, so every load is issued PREFETCH
+    // groups ahead of its use.  The body is branch-free: reloads are
+    // unconditional and clamped to the wave's last group, and a group
+    // index past the end repeats the last group with no valid points.
+    // Every wait then counts exactly the loads in flight.
+    const uint32_t glast = wave + (nj - 1) * WAVES;
+    Words R[PREFETCH];
+    uint32_t gi[PREFETCH];
+#pragma unroll
+    for (int d = 0; d < PREFETCH; ++d) {
+      gi[d] = wave + d * WAVES;
+      R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
+      // keep the initial loads in the order of their use, the order the
+      // loop reissues them in: the loop's waits then count PREFETCH - 1
+      // younger loads on every path
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (uint32_t j = 0; j < nj; j += PREFETCH) {
+#pragma unroll
+      for (int d = 0; d < PREFETCH; ++d) {
+        const uint32_t g = gi[d];
+        four_points<K, CLS, TILED, ACC>(L, tile, R[d], first + min(g, glast) * 256 + lane * 4,
+                                        g <= glast ? 4u : 0u, natom);
+        gi[d] = g + PREFETCH * WAVES;
+        R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
+      }
+    }
+  }
+  const uint32_t rem = count & 255u;
+  if (rem && wave == 0) {  // ragged tail of the batch: scalar loads, per-point bounds
+    const uint32_t j0 = ngrp * 256 + lane * 4;
+    const uint32_t nv = j0 < count ? min(4u, count - j0) : 0u;
+    uint32_t l[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0}, h[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if ((uint32_t)j < nv) {
+        l[j] = a.low[first + j0 + j];
+        if constexpr (K >= 20) m[j] = a.med[first + j0 + j];
+        if constexpr (K == 30) h[j] = a.high[first + j0 + j];
+        if constexpr (ACC) c[j] = a.colors[first + j0 + j];
+      }
+    }
+    Words t;
+    t.l = make_uint4(l[0], l[1], l[2], l[3]);
+    t.m = make_uint4(m[0], m[1], m[2], m[3]);
+    t.h = make_uint4(h[0], h[1], h[2], h[3]);
+    t.c = make_uint4(c[0], c[1], c[2], c[3]);
+    four_points<K, CLS, TILED, ACC>(L, tile, t, first + j0, nv, natom);
+  }
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// A uniform value as a VGPR operand (the pixel subtraction takes its carry
+// from an SGPR and may read only one scalar operand).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+  uint32_t v;
+  asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+  return v;
+}
+
+
+// ------------------------------------------------------------------ render
+template <int K, bool TILED, bool ACC = false>
+__device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const Streams& a, uint64_t* tile,
+                                                uint32_t first, uint32_t count, uint32_t wave, uint32_t lane,
+                                                uint32_t& natom) {
+  if (cls == CLS_INSIDE)
+    raster_points<K, CLS_INSIDE, TILED, ACC>(L, a, tile, first, count, wave, lane, natom);
+  else if (cls == CLS_PARTIAL)
+    raster_points<K, CLS_PARTIAL, TILED, ACC>(L, a, tile, first, count, wave, lane, natom);
+  else if constexpr (!TILED)
+    raster_points<K, CLS_SLOW, false, ACC>(L, a, tile, first, count, wave, lane, natom);
+}
+
+// One live batch of one view by the whole workgroup: its points into the LDS
+// tile (or straight into the global buffer), then the tile flush.  The LDS
+// tile is all PR_EMPTY between batches (the flush resets what it reads), so a
+// batch needs two barriers: one after its points, one after its flush.
+// publish: thread 0 stores next into s_next between the barriers (the
+// workgroup reads it after the second one).
+__device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, uint32_t H, uint64_t* vb,
+                                             const Streams& st, uint64_t* tile, uint32_t tid, uint32_t wave,
+                                             uint32_t lane, bool publish, uint32_t next, uint32_t* s_next,
+                                             uint32_t& natom) {
+  Loop L;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) L.P[r][j] = rec.P[r][j];
+    L.t[r] = rec.t[r];
+  }
+  L.W = W;
+  L.H = H;
+  L.vb = vb;
+  const uint32_t mode = rec.mode, rxy = rec.rect_xy, rwh = rec.rect_wh;
+  const uint32_t first = rec.first, count = rec.count;
+  const uint32_t x0 = rxy & 0xFFFFu, y0 = rxy >> 16;
+  L.tw = rwh & 0xFFFFu;
+  L.th = rwh >> 16;
+  L.tw8 = L.tw * 8u;
+  const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
+  const bool tiled = (mode >> 16) & 1u;
+  L.cx = in_vgpr(uni(0x4B000000u + (tiled ? x0 : 0u)));
+  L.cy = in_vgpr(uni(0x4B000000u + (tiled ? y0 : 0u)));
+  if (tiled) {
+    if (k == 10) raster_by_class<10, true>(cls, L, st, tile, first, count, wave, lane, natom);
+    else if (k == 20) raster_by_class<20, true>(cls, L, st, tile, first, count, wave, lane, natom);
+    else raster_by_class<30, true>(cls, L, st, tile, first, count, wave, lane, natom);
+  } else {
+    if (k == 10) raster_by_class<10, false>(cls, L, st, tile, first, count, wave, lane, natom);
+    else if (k == 20) raster_by_class<20, false>(cls, L, st, tile, first, count, wave, lane, natom);
+    else raster_by_class<30, false>(cls, L, st, tile, first, count, wave, lane, natom);
+  }
+  __syncthreads();  // the batch's points are all in the tile; s_next has been read
+  if (publish && tid == 0) *s_next = next;
+  if (tiled) {
+    // Flush: every covered tile pixel once into the global buffer, leaving
+    // the entry PR_EMPTY for the next batch.  Most covered pixels improve
+    // the global minimum, so the atomic is issued without a prior read
+    // (no round trip on this path).
+    const uint32_t n = L.tw * L.th;
+    for (uint32_t e = tid; e < n; e += THREADS) {
+      const uint64_t v = tile[e];
+      if (v != ~0ull) {
+        tile[e] = ~0ull;
+        const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
+        __hip_atomic_fetch_min(L.vb + ((y0 + ly) * L.W + (x0 + lx)), v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        natom++;
+      }
+    }
+  }
+  __syncthreads();  // tile clean again; s_next visible
+}
+
+__device__ __forceinline__ void fill_tile(uint64_t* tile, uint32_t tid) {
+  const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+  for (uint32_t e = tid; e < TILE_MAX / 2; e += THREADS) reinterpret_cast<uint4*>(tile)[e] = ones;
+}
+
+template <bool CNT>
+__device__ __forceinline__ void add_atomics(uint64_t* stats, uint32_t natom, uint32_t lane) {
+  if constexpr (CNT) {
+    for (int o = 32; o > 0; o >>= 1) natom += __shfl_xor(natom, o);
+    if (lane == 0 && natom) atomicAdd((unsigned long long*)&stats[ST_ATOMICS], (unsigned long long)natom);
+  }
+}
+
+// Persistent: each workgroup takes live batches from its work queue until it
+// is empty.  The next batch is requested while the current one renders.
+// The shape (SW waves, SD groups in flight, ST tile pixels) is among the
+// render kernels' template arguments only so that profiles name the shape
+// that ran; it must equal the translation unit's shape.
+template <bool CNT, int SW, int SD, int ST>
+__global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
+  static_assert(SW == WAVES && SD == PREFETCH && ST == (int)TILE_MAX, "shape tag");
+  __shared__ uint64_t tile[TILE_MAX];
+  __shared__ uint32_t s_next;
+  const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
+  fill_tile(tile, tid);
+  // this workgroup's queue: workgroups are spread over the queues round-robin
+  const uint32_t q = blockIdx.x % RENDER_QUEUES;
+  uint32_t* const qc = &a.hdr->queue[q][0];
+  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+  const uint32_t nlive = a.hdr->live_count;
+  const Streams st = {a.low, a.med, a.high, nullptr};
+  __syncthreads();
+  uint32_t i = uni(s_next);
+  uint32_t natom = 0;
+  while (i < nlive) {
+    // Take the next batch now; the atomic's latency hides behind this batch.
+    uint32_t grab = 0;
+    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    render_batch(a.live[i], a.W, a.H, a.vb, st, tile, tid, wave, lane, true, grab, &s_next, natom);
+    i = uni(s_next);
+  }
+  add_atomics<CNT>(a.stats, natom, lane);
+}
+
+// Several views in one launch: the work items are runs (a batch and its live
+// views); the workgroup renders the batch once per view, so its coordinate
+// words come from HBM once and from the caches for the further views.
+template <bool CNT, int SW, int SD, int ST>
+__global__ void __launch_bounds__(THREADS) k_render_views(RenderViewsArgs a) {
+  static_assert(SW == WAVES && SD == PREFETCH && ST == (int)TILE_MAX, "shape tag");
+  __shared__ uint64_t tile[TILE_MAX];
+  __shared__ uint32_t s_next;
+  const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
+  fill_tile(tile, tid);
+  const uint32_t q = blockIdx.x % RENDER_QUEUES;
+  uint32_t* const qc = &a.hdr->queue[q][0];
+  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+  const uint32_t nruns = a.hdr->live_count;
+  const Streams st = {a.low, a.med, a.high, nullptr};
+  __syncthreads();
+  uint32_t i = uni(s_next);
+  uint32_t natom = 0;
+  while (i < nruns) {
+    uint32_t grab = 0;
+    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    const Run run = a.runs[i];
+    uint64_t mask = run.mask;
+    bool publish = true;
+    while (mask) {
+      const uint32_t v = run.view0 + (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+      mask &= mask - 1;
+      const ViewOut& vo = a.v[v];
+      render_batch(a.sub[(uint64_t)run.batch * a.nviews + v], vo.W, vo.H, vo.vb, st, tile, tid, wave, lane, publish,
+                   grab, &s_next, natom);
+      publish = false;
+    }
+    i = uni(s_next);
+  }
+  add_atomics<CNT>(a.stats, natom, lane);
+}
+
+}  // namespace
+}  // namespace ptr
+
+#endif  // PR_RASTER_CORE_H

@@ -228,6 +228,12 @@ def served_camera(rng: np.random.Generator, seed: int, width: int, height: int) 
     return camera(eye, eye + fwd, (0.0, 0.0, 1.0), 60.0, width, height, 0.5, 5000.0)
 
 
+def camera_array(seed: int, n: int = 64, width: int = 1024, height: int = 1024, rng_seed: int = 64):
+    """n cameras over the terrain of `seed`, each drawn as served_camera (the multi-view workload's camera array)."""
+    rng = np.random.default_rng(rng_seed)
+    return [served_camera(rng, seed, width, height) for _ in range(n)]
+
+
 def request_stream(seed: int, n: int, rate: float, cloud_seeds, sizes=SERVED_SIZES):
     """n requests of a Poisson stream at `rate` per second: (arrival s, cloud index, Camera), in arrival order;
     uniform cloud and image size, camera by served_camera over that cloud's terrain."""

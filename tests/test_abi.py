@@ -91,3 +91,29 @@ def test_binding_has_no_fallback_path():
         if f.endswith(".py"):
             src = open(os.path.join(pkg, f)).read()
             assert "oracle" not in src and "synth" not in src, f
+
+
+def test_tuning_abi(pr):
+    lib = pr.lib
+    assert ctypes.sizeof(pr.Tuning) == 16 and ctypes.sizeof(pr.TuneTrial) == 24
+    assert ctypes.sizeof(pr.RasterShape) == 16
+    n = ctypes.c_uint32()
+    assert lib.pr_raster_shapes(None, None, 0, ctypes.byref(n)) == -1
+    assert lib.pr_set_tuning(None, None) == -1
+    assert lib.pr_get_tuning(None, None) == -1
+    assert lib.pr_autotune(None, None, None, 0, None, None, 0, 0, None, 0, None, None) == -1
+
+
+def test_every_listed_shape_is_compiled_in(pr):
+    """Each workgroup shape of the build's list is a translation unit of its own in the library."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("_b", os.path.join(ROOT, "paper_2204_01287_amd", "build.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    shapes = b.shapes()
+    assert shapes[0] == (4, 5, 4096) and len(set(shapes)) == len(shapes)
+    out = subprocess.run(["nm", "-C", "--defined-only", pr.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    for w, d, t in shapes:
+        assert f"ptr::raster_shape_w{w}_d{d}_t{t}()" in out, (w, d, t)
