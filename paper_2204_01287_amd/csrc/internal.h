@@ -157,7 +157,7 @@ struct RasterShape {
 // The compiled shapes: X(waves, depth, tile).  The first is the default.
 #define PR_RASTER_SHAPES(X)                                                                                  \
   X(4, 5, 4096) X(4, 3, 4096) X(4, 4, 4096) X(4, 6, 4096) X(4, 5, 2048) X(2, 5, 2048) X(2, 5, 4096)        \
-  X(8, 5, 8192) X(1, 5, 1024)
+  X(8, 5, 8192) X(1, 5, 1024) X(16, 5, 16384) X(16, 4, 16384) X(8, 5, 16384)
 #define PR_SHAPE_NAME_(W_, D_, T_) raster_shape_w##W_##_d##D_##_t##T_
 #define PR_SHAPE_NAME(W_, D_, T_) PR_SHAPE_NAME_(W_, D_, T_)
 #define PR_DECLARE_SHAPE(W_, D_, T_) const RasterShape* PR_SHAPE_NAME_(W_, D_, T_)();

@@ -32,7 +32,7 @@ constexpr int THREADS = 64 * WAVES;
 constexpr uint32_t TILE_MAX = PR_TILE;  // LDS tile of 64-bit keys
 constexpr int PREFETCH = PR_DEPTH;      // groups of 256 points in flight per wave
 static_assert(WAVES >= 1 && WAVES <= 16 && PREFETCH >= 1 && PREFETCH <= 8, "workgroup shape");
-static_assert(TILE_MAX >= 256 && TILE_MAX % (2 * 64) == 0 && TILE_MAX * 8 <= 65536, "LDS tile");
+static_assert(TILE_MAX >= 256 && TILE_MAX % (2 * 64) == 0 && TILE_MAX * 8 <= 131072, "LDS tile (160 KiB per CU)");
 
 // ------------------------------------------------------------------ render
 template <int K>
