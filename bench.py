@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpoints/s rendered + achieved HBM GB/s; p50/p99 frame latency in served mode"
 HBM_PEAK_GBS = 8000.0
+# plain (unpacked) VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD every 4 cycles
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 
 
 def log(msg):
@@ -159,18 +161,44 @@ def cpu_baseline(wl, sample_n: int, seconds: float):
                        f"{secs:.1f} s; oracle build {t_build:.1f} s not included; single thread")
 
 
-def traffic_from_profiles(kernel_src_hash: str, workload_name: str):
-    """HBM bytes per render launch from committed rocprofv3 --pmc summaries, if they match this kernel."""
-    path = os.path.join(ROOT, "profiles", f"render_{workload_name}_hbm_traffic.json")
+def profile_counters(kernel_src_hash: str, workload_name: str) -> dict:
+    """Counters of the render kernel (HBM bytes, VALU instructions per launch) from the committed rocprofv3 --pmc
+    summary, if it was taken on these kernel sources; else {}."""
+    path = os.path.join(ROOT, "profiles", f"render_{workload_name}_counters.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         d = json.load(open(path))
     except Exception:
-        return None
+        return {}
     if d.get("kernel_src_sha256") != kernel_src_hash:
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return {}
+    return d
+
+
+def measure_stream(pr, ctx, nbytes: int = 4 << 30, reps: int = 10) -> dict:
+    """Streaming ceiling of this device, from the library's own probe kernels: GB/s of a read-only pass over
+    2 x nbytes and of a copy of nbytes (read + write counted), mean over reps launches each after two untimed."""
+    import torch
+
+    a = torch.ones(2 * nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, src, dst, moved in (("read", a, None, 2 * nbytes), ("copy", a, b, 2 * nbytes)):
+        nb = 2 * nbytes if dst is None else nbytes
+        for _ in range(2):
+            pr.pr_stream_probe(ctx.handle, src, dst, nb)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            pr.pr_stream_probe(ctx.handle, src, dst, nb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = round(moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def kernel_hash():
@@ -561,17 +589,19 @@ def main():
     import numpy as np
     import torch
 
+    import paper_2204_01287_amd as pr
+
     if args.calib_copy:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        ctx = pr.Context(0)
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(5):
-            torch.add(a, 0.0, out=b)
-        torch.cuda.synchronize()
-        print(json.dumps({"calib_copy_bytes_read": a.numel() * 4, "calib_copy_bytes_written": b.numel() * 4,
-                          "launches": 5}))
+            pr.pr_stream_probe(ctx.handle, a, b, a.numel() * 4)
+        pr.pr_sync(ctx.handle)
+        print(json.dumps({"calib_copy_kernel": "k_stream_copy", "calib_copy_bytes_read": a.numel() * 4,
+                          "calib_copy_bytes_written": b.numel() * 4, "launches": 5}))
+        ctx.close()
         return
-
-    import paper_2204_01287_amd as pr
 
     wl = workload(args.workload, args.n)
     # everything runs on one side stream, so that frames can be captured into HIP graphs
@@ -631,7 +661,10 @@ def main():
     value = processed / (ms_per_step * 1e-3) / 1e9
     mean_render = [float(np.mean(r)) for r in render_ms]
     achieved = sum(alg_bytes) / (sum(mean_render) * 1e-3) / 1e9  # GB/s over the render launches
-    traffic = traffic_from_profiles(kernel_hash(), wl["name"])
+    stream_peak = measure_stream(pr, ctx)  # after the frames: clocks as in the timed region
+    log(f"streaming probe: {stream_peak}")
+    prof = profile_counters(kernel_hash(), wl["name"])
+    traffic = prof.get("hbm_bytes_per_launch")
     log(f"wall {wall:.3f} s for {args.steps} steps; events {ms_per_step:.3f} ms/step; render {mean_render} ms; "
         f"clear {np.mean(clear_ms):.4f} ms; resolve {np.mean(resolve_ms):.4f} ms")
 
@@ -658,8 +691,27 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "render", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes_per_launch": [int(b) for b in alg_bytes],
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "measured_stream_gbs": stream_peak,
+                     "frac_of_measured_read": round(achieved / stream_peak["read"], 4)},
     }
+    if prof.get("valu_insts_per_launch"):
+        # VALU issue beside HBM: wave64 VALU instructions of one render launch (SQ_INSTS_VALU, committed
+        # profile of these sources) over the launch's mean duration
+        rate = prof["valu_insts_per_launch"] / (float(np.mean(mean_render)) * 1e-3)
+        out["valu_roofline"] = {"bound": "alu", "kernel": "render", "achieved": round(rate * 64 / 1e12, 2),
+                                "peak": round(VALU_PEAK_WAVE_INSTS * 64 / 1e12, 2),
+                                "unit": "T lane-ops/s (wave64 VALU instructions x 64)",
+                                "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4),
+                                "valu_insts_per_launch": prof["valu_insts_per_launch"]}
+    # the same ceiling against the method's own operation count per processed point (unpack 3, convert 3,
+    # FMA 9, w test 1, two exact floors, two bounds checks, one 64-bit compare: 20)
+    alg_ops = 20 * processed / len(cams) / (float(np.mean(mean_render)) * 1e-3)
+    out.setdefault("valu_roofline", {"bound": "alu", "kernel": "render",
+                                     "peak": round(VALU_PEAK_WAVE_INSTS * 64 / 1e12, 2)})
+    out["valu_roofline"]["algorithmic_ops_per_point"] = 20
+    out["valu_roofline"]["algorithmic_achieved"] = round(alg_ops / 1e12, 2)
+    out["valu_roofline"]["algorithmic_frac"] = round(alg_ops / (VALU_PEAK_WAVE_INSTS * 64), 4)
     out["multiview"] = multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, ms_per_step,
                                             args.steps, args.warmup)
     out["hqs"] = hqs_leg(pr, ctx, cloud, cams, processed, args.steps, args.warmup)

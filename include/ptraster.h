@@ -323,6 +323,16 @@ pr_status pr_autotune(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, 
                       const pr_render_opts* opts, void* work, uint64_t work_bytes, uint32_t reps,
                       pr_tune_trial* trials, uint32_t cap, uint32_t* ntrials, pr_tuning* best);
 
+/* ---- HBM streaming reference (not part of the method) ----
+ * A plain vectorised grid-stride kernel over bytes bytes of device memory
+ * (bytes a multiple of 16, pointers 16-byte aligned): copies src to dst, or,
+ * with dst NULL, only reads src.  Its measured rate is the streaming ceiling
+ * the render kernel's HBM roofline is reported beside, and the copy is a
+ * kernel of known traffic for calibrating HBM byte counters.  Asynchronous on
+ * the context's stream.  PR_EINVAL for NULL src, a size that is not a
+ * multiple of 16 or misaligned pointers. */
+pr_status pr_stream_probe(pr_ctx* ctx, const void* src, void* dst, uint64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_lo
             "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
             "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers", "pr_render_hqs",
             "pr_cloud_sizes_spans", "pr_build_batches_spans", "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning",
-            "pr_autotune"]
+            "pr_autotune", "pr_stream_probe"]
 
 
 class PrError(RuntimeError):
@@ -119,6 +119,7 @@ lib.pr_render_hqs.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderO
 lib.pr_render_views.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64]
 lib.pr_sync.argtypes = [_P]
 lib.pr_raster_shapes.argtypes = [_P, ctypes.POINTER(RasterShape), _U32, ctypes.POINTER(_U32)]
+lib.pr_stream_probe.argtypes = [_P, _P, _P, _U64]
 lib.pr_set_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
 lib.pr_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
 lib.pr_autotune.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64, _U32,
@@ -129,7 +130,7 @@ lib.pr_cloud_free.restype = None
 for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
            "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views",
            "pr_cloud_drop_load_buffers", "pr_render_hqs", "pr_cloud_sizes_spans", "pr_build_batches_spans",
-           "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning", "pr_autotune"):
+           "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning", "pr_autotune", "pr_stream_probe"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -251,6 +252,11 @@ def pr_render_views(ctx, cloud, views, opts: RenderOpts | None, work, work_bytes
     _check(lib.pr_render_views(ctx, cloud, _views(views), len(views),
                                ctypes.byref(opts) if opts is not None else None, _ptr(work), work_bytes),
            "pr_render_views")
+
+
+def pr_stream_probe(ctx, src, dst, nbytes: int):
+    """HBM streaming reference: copy src -> dst (or, dst None, read src only), nbytes a multiple of 16."""
+    _check(lib.pr_stream_probe(ctx, _ptr(src), _ptr(dst), nbytes), "pr_stream_probe")
 
 
 def pr_raster_shapes(ctx) -> list:

@@ -23,6 +23,7 @@ static_assert(sizeof(LodNode) == 48, "LOD node record is 48 bytes");
 struct DevBlock {
   uint64_t stats[16];     // batches, culled, points, lvl_b[3], lvl_p[3], atomics
   uint32_t flags[16];     // [0] non-finite coordinate seen
+  uint64_t sink;          // streaming read probe
 };
 enum { ST_BATCHES = 0, ST_CULLED, ST_POINTS, ST_LB0, ST_LB1, ST_LB2, ST_LP0, ST_LP1, ST_LP2, ST_ATOMICS };
 
@@ -171,6 +172,9 @@ hipError_t launch_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* col
 hipError_t launch_accumulate(const RenderArgs& a, hipStream_t s);
 uint32_t accum_grid(int device);
 hipError_t launch_resolve_hqs(const uint64_t* accum, uint64_t npix, uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
+
+// ---- HBM streaming probes (kern_stream.hip): copy src -> dst, or (dst null) read src, XOR into *sink
+hipError_t launch_stream(const void* src, void* dst, uint64_t bytes, uint64_t* sink, uint32_t blocks, hipStream_t s);
 
 // ---- load-time build (kern_build.hip)
 struct SortScratch {

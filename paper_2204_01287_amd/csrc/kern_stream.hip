@@ -1,0 +1,69 @@
+// HBM streaming probes (not part of the method): a plain vectorised copy and a
+// read-only pass over a buffer.  They measure the streaming bandwidth the
+// device actually reaches, which the render kernel's HBM roofline is reported
+// beside, and the copy is a kernel of known traffic for calibrating HBM byte
+// counters.  Each lane keeps four 16-byte loads in flight; the grid strides
+// over the buffer in workgroup-contiguous chunks.
+#include "internal.h"
+
+namespace ptr {
+namespace {
+
+constexpr int UNROLL = 4;
+constexpr uint64_t CHUNK = 256 * UNROLL;  // 16-byte words per workgroup and step: one contiguous 16 KiB
+
+// Workgroup-contiguous chunks: lane t of step u touches word base + u * 256 + t,
+// so each load instruction of a wave covers 1 KiB of consecutive memory.
+__global__ void __launch_bounds__(256) k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                     uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * CHUNK;
+  for (uint64_t base = (uint64_t)blockIdx.x * CHUNK; base < n; base += stride) {
+    uint4 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint64_t k = base + u * 256u + threadIdx.x;
+      v[u] = k < n ? src[k] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint64_t k = base + u * 256u + threadIdx.x;
+      if (k < n) dst[k] = v[u];
+    }
+  }
+}
+
+// XOR of every word, folded per wave and combined with one atomic per wave
+// into *sink (the result keeps the loads from being optimised away).
+__global__ void __launch_bounds__(256) k_stream_read(const uint4* __restrict__ src, uint64_t n,
+                                                     uint64_t* __restrict__ sink) {
+  const uint64_t stride = (uint64_t)gridDim.x * CHUNK;
+  uint32_t acc = 0;
+  for (uint64_t base = (uint64_t)blockIdx.x * CHUNK; base < n; base += stride) {
+    uint4 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint64_t k = base + u * 256u + threadIdx.x;
+      v[u] = k < n ? src[k] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_xor(sink, (uint64_t)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+hipError_t launch_stream(const void* src, void* dst, uint64_t bytes, uint64_t* sink, uint32_t blocks,
+                         hipStream_t s) {
+  const uint64_t n = bytes / 16;
+  if (n == 0) return hipSuccess;
+  if (dst)
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, s, static_cast<const uint4*>(src),
+                       static_cast<uint4*>(dst), n);
+  else
+    hipLaunchKernelGGL(k_stream_read, dim3(blocks), dim3(256), 0, s, static_cast<const uint4*>(src), n, sink);
+  return hipGetLastError();
+}
+
+}  // namespace ptr

@@ -644,6 +644,15 @@ pr_status pr_cloud_info(const pr_cloud* cloud, uint64_t* n, uint64_t* nbatches, 
 
 void pr_cloud_free(pr_cloud* cloud) { delete cloud; }
 
+pr_status pr_stream_probe(pr_ctx* ctx, const void* src, void* dst, uint64_t bytes) {
+  if (!ctx || !src) return fail(PR_EINVAL, "pr_stream_probe: NULL argument");
+  if ((bytes & 15u) || (reinterpret_cast<uintptr_t>(src) & 15u) || (reinterpret_cast<uintptr_t>(dst) & 15u))
+    return fail(PR_EINVAL, "pr_stream_probe: size and pointers must be multiples of 16");
+  if (pr_status s = set_device(ctx)) return s;
+  HIP_TRY(ptr::launch_stream(src, dst, bytes, &ctx->dev->sink, 32u * ctx->cus, ctx->stream), "stream probe");
+  return PR_OK;
+}
+
 pr_status pr_raster_shapes(const pr_ctx* ctx, pr_raster_shape* out, uint32_t cap, uint32_t* count) {
   if (!ctx || !count || (cap && !out)) return fail(PR_EINVAL, "pr_raster_shapes: NULL argument");
   for (uint32_t i = 0; i < kNumShapes && i < cap; ++i)
