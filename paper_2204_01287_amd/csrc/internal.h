@@ -42,12 +42,15 @@ static_assert(sizeof(LiveBatch) == 80, "live batch record is 80 bytes");
 
 // Per-frame counters of the render path (in the cloud's scratch area).  The
 // live batches are handed out through RENDER_QUEUES work queues (queue q
-// owns live batches q, q + RENDER_QUEUES, ...), each counter on its own
+// owns queue positions q, q + RENDER_QUEUES, ...), each counter on its own
 // 128-byte line: one shared counter serialises every workgroup's request.
+// A position maps to a live-list slot with the untiled batches spread evenly
+// among the tiled ones (live_slot in raster_core.h).
 constexpr uint32_t RENDER_QUEUES = 8;
 struct FrameHeader {
-  uint32_t live_count;  // live batches (single view) or runs (several views) written by classify
-  uint32_t pad[31];
+  uint32_t live_count;    // tiled live batches (single view, from the front) or runs (several views)
+  uint32_t direct_count;  // untiled live batches (single view), stored from the back of the list
+  uint32_t pad[30];
   uint32_t queue[RENDER_QUEUES][32];  // queue[q][0]: next position of queue q
 };
 static_assert(sizeof(FrameHeader) == 128 * (1 + RENDER_QUEUES), "frame header layout");

@@ -28,15 +28,15 @@ __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
   const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
   const uint32_t q = blockIdx.x % RENDER_QUEUES;
   uint32_t* const qc = &a.hdr->queue[q][0];
-  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
-  const uint32_t nlive = a.hdr->live_count;
+  const uint32_t nt = a.hdr->live_count, nd = a.hdr->direct_count;
+  if (tid == 0) s_next = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.nb);
   const Streams st = {a.low, a.med, a.high, a.colors};
   __syncthreads();
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
-  while (i < nlive) {
+  while (i != ~0u) {
     uint32_t grab = 0;
-    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    if (tid == 0) grab = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.nb);
     const LiveBatch& rec = a.live[i];
     Loop L;
 #pragma unroll

@@ -17,8 +17,11 @@
 // Sec. 3.2 / 3.3 for every batch at once (one thread per batch): it projects
 // the 8 box corners, culls, picks the precision level, folds the decode into
 // the batch matrix, and appends the surviving batches to a compact list with
-// a wave ballot.  The persistent render kernel then hands the live batches to
-// its workgroups through atomic work queues.  Classes:
+// a wave ballot (tiled batches from its front, untiled ones from its back).
+// The persistent render kernel then hands the live batches to its workgroups
+// through atomic work queues, the untiled ones (whose points go to the global
+// atomic minimum one by one) spread evenly over the frame: concentrated, their
+// atomics contend and the frame is slower.  Classes:
 //  CULLED  : some frustum plane has all corners outside by a margin that
 //            exceeds every rounding of the per-point evaluation;
 //  INSIDE  : all corners strictly inside every plane by that margin and w in
@@ -57,7 +60,10 @@ __global__ void __launch_bounds__(256) k_clear(uint4* __restrict__ vb4, uint64_t
   for (uint64_t i = tid; i < n4; i += stride) vb4[i] = ones;
   if (tid == 0 && (npix & 1)) vb[npix - 1] = ~0ull;
   if (blockIdx.x == 0) {
-    if (hdr && threadIdx.x == 0) hdr->live_count = 0;
+    if (hdr && threadIdx.x == 0) {
+      hdr->live_count = 0;
+      hdr->direct_count = 0;
+    }
     if (hdr && threadIdx.x < RENDER_QUEUES) hdr->queue[threadIdx.x][0] = 0;
     if (reset_stats && threadIdx.x < 16) dev->stats[threadIdx.x] = 0;
   }
@@ -255,14 +261,17 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
       }
     }
   }
-  const uint64_t m = __ballot(live);
-  uint32_t base = 0;
-  if (lane == 0 && m) base = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(m));
-  base = __shfl(base, 0);
-  if (live) {
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    a.live[base + (uint32_t)__popcll(m & lt)] = out;
-  }
+  // tiled batches from the front of the list, untiled ones from the back
+  const bool tiled = live && ((out.mode >> 16) & 1u);
+  const uint64_t mt = __ballot(tiled), md = __ballot(live && !tiled);
+  uint32_t bt = 0, bd = 0;
+  if (lane == 0 && mt) bt = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(mt));
+  if (lane == 0 && md) bd = atomicAdd(&a.hdr->direct_count, (uint32_t)__popcll(md));
+  bt = __shfl(bt, 0);
+  bd = __shfl(bd, 0);
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (tiled) a.live[bt + (uint32_t)__popcll(mt & lt)] = out;
+  else if (live) a.live[a.nb - 1u - (bd + (uint32_t)__popcll(md & lt))] = out;
 }
 
 // Several views: one thread per batch runs the prologue for each view of

@@ -428,6 +428,19 @@ __device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, u
   __syncthreads();  // tile clean again; s_next visible
 }
 
+// The live list holds nt tiled batches from the front and nd untiled ones
+// from the back (slots nb - 1, nb - 2, ...).  Queue position p of n = nt + nd
+// takes an untiled batch iff floor((p + 1) nd / n) > floor(p nd / n), which
+// spreads the untiled batches (and their global atomics) evenly over the
+// frame.  Returns ~0u past the end.
+__device__ __forceinline__ uint32_t live_slot(uint32_t p, uint32_t nt, uint32_t nd, uint32_t nb) {
+  const uint32_t n = nt + nd;
+  if (p >= n) return ~0u;
+  if (nd == 0) return p;
+  const uint32_t k = (uint32_t)(((uint64_t)p * nd) / n), k1 = (uint32_t)(((uint64_t)(p + 1) * nd) / n);
+  return k1 > k ? nb - 1u - k : p - k;
+}
+
 __device__ __forceinline__ void fill_tile(uint64_t* tile, uint32_t tid) {
   const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
   for (uint32_t e = tid; e < TILE_MAX / 2; e += THREADS) reinterpret_cast<uint4*>(tile)[e] = ones;
@@ -456,16 +469,16 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
   // this workgroup's queue: workgroups are spread over the queues round-robin
   const uint32_t q = blockIdx.x % RENDER_QUEUES;
   uint32_t* const qc = &a.hdr->queue[q][0];
-  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
-  const uint32_t nlive = a.hdr->live_count;
+  const uint32_t nt = a.hdr->live_count, nd = a.hdr->direct_count;
+  if (tid == 0) s_next = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.nb);
   const Streams st = {a.low, a.med, a.high, nullptr};
   __syncthreads();
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
-  while (i < nlive) {
+  while (i != ~0u) {
     // Take the next batch now; the atomic's latency hides behind this batch.
     uint32_t grab = 0;
-    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    if (tid == 0) grab = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.nb);
     render_batch(a.live[i], a.W, a.H, a.vb, st, tile, tid, wave, lane, true, grab, &s_next, natom);
     i = uni(s_next);
   }
