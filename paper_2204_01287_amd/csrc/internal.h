@@ -48,8 +48,8 @@ static_assert(sizeof(LiveBatch) == 80, "live batch record is 80 bytes");
 // among the tiled ones (live_slot in raster_core.h).
 constexpr uint32_t RENDER_QUEUES = 8;
 struct FrameHeader {
-  uint32_t live_count;    // tiled live batches (single view, from the front) or runs (several views)
-  uint32_t direct_count;  // untiled live batches (single view), stored from the back of the list
+  uint32_t live_count;    // tiled live batches / runs with a tiled view, stored from the front of the list
+  uint32_t direct_count;  // untiled live batches / runs with no tiled view, stored from the back
   uint32_t pad[30];
   uint32_t queue[RENDER_QUEUES][32];  // queue[q][0]: next position of queue q
 };
@@ -111,6 +111,7 @@ struct ClassifyViewsArgs {
   const LodNode* nodes;
   float lod_px;
   uint32_t tile_max;
+  uint32_t cap;  // run slots (one per batch and classify launch)
   ViewIn v[VIEW_CHUNK];
 };
 struct RenderViewsArgs {
@@ -121,7 +122,7 @@ struct RenderViewsArgs {
   const Run* runs;
   FrameHeader* hdr;
   uint64_t* stats;
-  uint32_t nviews, grid;
+  uint32_t nviews, grid, cap;
   ViewOut v[MAX_VIEWS];
 };
 struct ClearViewsArgs {

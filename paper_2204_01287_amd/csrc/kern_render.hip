@@ -276,13 +276,15 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
 
 // Several views: one thread per batch runs the prologue for each view of
 // this launch; the records go to fixed slots (batch, view), the batch's live
-// views to one run record (wave ballot + one atomic per wave).
+// views to one run record (wave ballot + one atomic per wave): from the back
+// of the run list if no live view is tiled, else from its front.
 template <bool CNT>
 __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
   const uint32_t b = blockIdx.x * 256u + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63;
   const bool valid = b < a.nb;
   uint64_t mask = 0;
+  bool tiled_any = false;
   uint64_t nculled = 0, pts = 0, lp[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
   if (valid) {
     const BatchRec rec = a.batches[b];
@@ -294,6 +296,7 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
                        a.nodes ? a.nodes + b : nullptr, a.lod_px, a.tile_max, out, culled, li)) {
         a.sub[(uint64_t)b * a.nviews + a.view0 + v] = out;
         mask |= 1ull << v;
+        tiled_any = tiled_any || ((out.mode >> 16) & 1u);
         if constexpr (CNT) {
           pts += rec.count;
           lp[li] += rec.count;
@@ -324,18 +327,21 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
       }
     }
   }
-  const bool live = mask != 0;
-  const uint64_t m = __ballot(live);
-  uint32_t base = 0;
-  if (lane == 0 && m) base = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(m));
-  base = __shfl(base, 0);
+  const bool live = mask != 0, direct = live && !tiled_any;
+  const uint64_t mt = __ballot(live && !direct), md = __ballot(direct);
+  uint32_t bt = 0, bd = 0;
+  if (lane == 0 && mt) bt = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(mt));
+  if (lane == 0 && md) bd = atomicAdd(&a.hdr->direct_count, (uint32_t)__popcll(md));
+  bt = __shfl(bt, 0);
+  bd = __shfl(bd, 0);
   if (live) {
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     Run r;
     r.batch = b;
     r.view0 = a.view0;
     r.mask = mask;
-    a.runs[base + (uint32_t)__popcll(m & lt)] = r;
+    if (direct) a.runs[a.cap - 1u - (bd + (uint32_t)__popcll(md & lt))] = r;
+    else a.runs[bt + (uint32_t)__popcll(mt & lt)] = r;
   }
 }
 
@@ -353,7 +359,10 @@ __global__ void __launch_bounds__(256) k_clear_views(ClearViewsArgs a) {
     if (tid == 0 && (npix & 1)) v.vb[npix - 1] = ~0ull;
   }
   if (blockIdx.x == 0 && blockIdx.y == 0) {
-    if (threadIdx.x == 0) a.hdr->live_count = 0;
+    if (threadIdx.x == 0) {
+      a.hdr->live_count = 0;
+      a.hdr->direct_count = 0;
+    }
     if (threadIdx.x < RENDER_QUEUES) a.hdr->queue[threadIdx.x][0] = 0;
     if (a.reset_stats && threadIdx.x < 16) a.stats[threadIdx.x] = 0;
   }

@@ -527,6 +527,9 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
   const pr_tuning tune = ctx->tuning;
   const uint64_t nb = cloud->nb;
   const uint32_t nchunks = (nviews + ptr::VIEW_CHUNK - 1) / ptr::VIEW_CHUNK;
+  if (nb * nchunks > 0xFFFFFFFFull)
+    return fail(PR_ERANGE, "pr_render_views: %llu batches x %u classify launches exceed 2^32 run slots",
+                (unsigned long long)nb, nchunks);
   ptr::FrameHeader* hdr = static_cast<ptr::FrameHeader*>(work);
   ptr::Run* runs = reinterpret_cast<ptr::Run*>(hdr + 1);
   ptr::LiveBatch* sub = reinterpret_cast<ptr::LiveBatch*>(runs + nb * nchunks);
@@ -560,6 +563,7 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
     k.nodes = cloud->lod ? static_cast<const ptr::LodNode*>(cloud->bufs.nodes) : nullptr;
     k.lod_px = o.lod_px;
     k.tile_max = shape_tile(tune);
+    k.cap = (uint32_t)(nb * nchunks);
     for (uint32_t v = 0; v < k.nchunk; ++v) {
       const pr_view& pv = views[k.view0 + v];
       frame_matrix(pv.view, pv.proj, pv.w, pv.h, k.v[v].Pm);
@@ -580,6 +584,7 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
   r.stats = ctx->dev->stats;
   r.nviews = nviews;
   r.grid = shape_grid(ctx, tune, 1);
+  r.cap = (uint32_t)(nb * nchunks);
   for (uint32_t v = 0; v < nviews; ++v) r.v[v] = {views[v].visbuf, views[v].w, views[v].h};
   HIP_TRY(shape_of(tune).render_views(r, nb * nchunks, o.counters ? 1 : 0, ctx->stream), "render views");
   return PR_OK;

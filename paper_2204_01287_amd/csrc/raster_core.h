@@ -428,11 +428,11 @@ __device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, u
   __syncthreads();  // tile clean again; s_next visible
 }
 
-// The live list holds nt tiled batches from the front and nd untiled ones
-// from the back (slots nb - 1, nb - 2, ...).  Queue position p of n = nt + nd
-// takes an untiled batch iff floor((p + 1) nd / n) > floor(p nd / n), which
-// spreads the untiled batches (and their global atomics) evenly over the
-// frame.  Returns ~0u past the end.
+// The live list (or run list) of nb slots holds nt tiled entries from the
+// front and nd entries with untiled batches from the back (slots nb - 1,
+// nb - 2, ...).  Queue position p of n = nt + nd takes an untiled one iff
+// floor((p + 1) nd / n) > floor(p nd / n), which spreads the untiled batches
+// (and their global atomics) evenly over the frame.  Returns ~0u past the end.
 __device__ __forceinline__ uint32_t live_slot(uint32_t p, uint32_t nt, uint32_t nd, uint32_t nb) {
   const uint32_t n = nt + nd;
   if (p >= n) return ~0u;
@@ -497,15 +497,15 @@ __global__ void __launch_bounds__(THREADS) k_render_views(RenderViewsArgs a) {
   fill_tile(tile, tid);
   const uint32_t q = blockIdx.x % RENDER_QUEUES;
   uint32_t* const qc = &a.hdr->queue[q][0];
-  if (tid == 0) s_next = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
-  const uint32_t nruns = a.hdr->live_count;
+  const uint32_t nt = a.hdr->live_count, nd = a.hdr->direct_count;
+  if (tid == 0) s_next = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.cap);
   const Streams st = {a.low, a.med, a.high, nullptr};
   __syncthreads();
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
-  while (i < nruns) {
+  while (i != ~0u) {
     uint32_t grab = 0;
-    if (tid == 0) grab = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    if (tid == 0) grab = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.cap);
     const Run run = a.runs[i];
     uint64_t mask = run.mask;
     bool publish = true;
