@@ -50,12 +50,14 @@ constexpr uint32_t RENDER_QUEUES = 8;
 struct FrameHeader {
   uint32_t live_count;    // tiled live batches / runs with a tiled view, stored from the front of the list
   uint32_t direct_count;  // untiled live batches / runs with no tiled view, stored from the back
-  uint32_t pad[30];
+  uint32_t order_count;   // single view: entries of the batch-order index (= live_count + direct_count)
+  uint32_t pad[29];
   uint32_t queue[RENDER_QUEUES][32];  // queue[q][0]: next position of queue q
 };
 static_assert(sizeof(FrameHeader) == 128 * (1 + RENDER_QUEUES), "frame header layout");
 
-inline uint64_t frame_area_bytes(uint64_t nb) { return sizeof(FrameHeader) + sizeof(LiveBatch) * nb; }
+// header, live list (nb records), batch-order index of the live list (nb slots)
+inline uint64_t frame_area_bytes(uint64_t nb) { return sizeof(FrameHeader) + (sizeof(LiveBatch) + 4) * nb; }
 
 struct RenderArgs {
   const uint32_t* low;
@@ -63,6 +65,7 @@ struct RenderArgs {
   const uint32_t* high;
   const BatchRec* batches;
   LiveBatch* live;
+  uint32_t* order;  // live-list slots in batch order (read by the shading pass)
   FrameHeader* hdr;
   uint64_t* vb;
   uint64_t* stats;

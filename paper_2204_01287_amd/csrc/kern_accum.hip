@@ -28,15 +28,23 @@ __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
   const uint32_t tid = threadIdx.x, wave = uni(tid >> 6), lane = tid & 63;
   const uint32_t q = blockIdx.x % RENDER_QUEUES;
   uint32_t* const qc = &a.hdr->queue[q][0];
-  const uint32_t nt = a.hdr->live_count, nd = a.hdr->direct_count;
-  if (tid == 0) s_next = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.nb);
+  // batch order (Morton order for sorted clouds): the sums' lines of neighbouring
+  // batches stay in the caches; measured faster than the render's order here
+  const uint32_t n = a.hdr->order_count;
+  if (tid == 0) {
+    const uint32_t p = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+    s_next = p < n ? a.order[p] : ~0u;
+  }
   const Streams st = {a.low, a.med, a.high, a.colors};
   __syncthreads();
   uint32_t i = uni(s_next);
   uint32_t natom = 0;
   while (i != ~0u) {
     uint32_t grab = 0;
-    if (tid == 0) grab = live_slot(atomicAdd(qc, 1u) * RENDER_QUEUES + q, nt, nd, a.nb);
+    if (tid == 0) {
+      const uint32_t p = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
+      grab = p < n ? a.order[p] : ~0u;
+    }
     const LiveBatch& rec = a.live[i];
     Loop L;
 #pragma unroll

@@ -63,6 +63,7 @@ __global__ void __launch_bounds__(256) k_clear(uint4* __restrict__ vb4, uint64_t
     if (hdr && threadIdx.x == 0) {
       hdr->live_count = 0;
       hdr->direct_count = 0;
+      hdr->order_count = 0;
     }
     if (hdr && threadIdx.x < RENDER_QUEUES) hdr->queue[threadIdx.x][0] = 0;
     if (reset_stats && threadIdx.x < 16) dev->stats[threadIdx.x] = 0;
@@ -270,8 +271,14 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
   bt = __shfl(bt, 0);
   bd = __shfl(bd, 0);
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  if (tiled) a.live[bt + (uint32_t)__popcll(mt & lt)] = out;
-  else if (live) a.live[a.nb - 1u - (bd + (uint32_t)__popcll(md & lt))] = out;
+  const uint32_t slot = tiled ? bt + (uint32_t)__popcll(mt & lt) : a.nb - 1u - (bd + (uint32_t)__popcll(md & lt));
+  if (live) a.live[slot] = out;
+  // and the slots in batch order, for the shading pass
+  const uint64_t ml = __ballot(live);
+  uint32_t bo = 0;
+  if (lane == 0 && ml) bo = atomicAdd(&a.hdr->order_count, (uint32_t)__popcll(ml));
+  bo = __shfl(bo, 0);
+  if (live) a.order[bo + (uint32_t)__popcll(ml & lt)] = slot;
 }
 
 // Several views: one thread per batch runs the prologue for each view of

@@ -32,8 +32,9 @@ __global__ void __launch_bounds__(256) k_stream_copy(const uint4* __restrict__ s
   }
 }
 
-// XOR of every word, folded per wave and combined with one atomic per wave
-// into *sink (the result keeps the loads from being optimised away).
+// XOR of the words each lane read; a lane stores it to *sink only if it
+// equals a marker value, which keeps the loads from being optimised away
+// without a store (or a contended atomic) per wave.
 __global__ void __launch_bounds__(256) k_stream_read(const uint4* __restrict__ src, uint64_t n,
                                                      uint64_t* __restrict__ sink) {
   const uint64_t stride = (uint64_t)gridDim.x * CHUNK;
@@ -48,8 +49,7 @@ __global__ void __launch_bounds__(256) k_stream_read(const uint4* __restrict__ s
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
   }
-  for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o);
-  if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_xor(sink, (uint64_t)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (acc == 0x9E3779B9u) *sink = acc;
 }
 
 }  // namespace
@@ -58,6 +58,8 @@ hipError_t launch_stream(const void* src, void* dst, uint64_t bytes, uint64_t* s
                          hipStream_t s) {
   const uint64_t n = bytes / 16;
   if (n == 0) return hipSuccess;
+  const uint64_t chunks = (n + CHUNK - 1) / CHUNK;
+  if (blocks > chunks) blocks = (uint32_t)chunks;
   if (dst)
     hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, s, static_cast<const uint4*>(src),
                        static_cast<uint4*>(dst), n);

@@ -428,6 +428,7 @@ pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16],
   a.batches = static_cast<const ptr::BatchRec*>(cloud->bufs.batches);
   a.hdr = hdr;
   a.live = reinterpret_cast<ptr::LiveBatch*>(hdr + 1);
+  a.order = reinterpret_cast<uint32_t*>(a.live + cloud->nb);
   const pr_tuning tune = ctx->tuning;
   a.grid = shape_grid(ctx, tune, 0);
   a.tile_max = shape_tile(tune);
@@ -654,7 +655,7 @@ pr_status pr_stream_probe(pr_ctx* ctx, const void* src, void* dst, uint64_t byte
   if ((bytes & 15u) || (reinterpret_cast<uintptr_t>(src) & 15u) || (reinterpret_cast<uintptr_t>(dst) & 15u))
     return fail(PR_EINVAL, "pr_stream_probe: size and pointers must be multiples of 16");
   if (pr_status s = set_device(ctx)) return s;
-  HIP_TRY(ptr::launch_stream(src, dst, bytes, &ctx->dev->sink, 32u * ctx->cus, ctx->stream), "stream probe");
+  HIP_TRY(ptr::launch_stream(src, dst, bytes, &ctx->dev->sink, 256u * ctx->cus, ctx->stream), "stream probe");
   return PR_OK;
 }
 
