@@ -2,6 +2,7 @@
 // libptraster.so.  Not part of the ABI (see include/ptraster.h).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace ptr {
@@ -48,13 +49,15 @@ static_assert(sizeof(LiveBatch) == 80, "live batch record is 80 bytes");
 // among the tiled ones (live_slot in raster_core.h).
 constexpr uint32_t RENDER_QUEUES = 8;
 struct FrameHeader {
+  // One 64-bit counter (classify adds tiled | untiled << 32 with one atomic
+  // per wave, so the two prefixes it returns come from one order):
   uint32_t live_count;    // tiled live batches / runs with a tiled view, stored from the front of the list
   uint32_t direct_count;  // untiled live batches / runs with no tiled view, stored from the back
-  uint32_t order_count;   // single view: entries of the batch-order index (= live_count + direct_count)
-  uint32_t pad[29];
+  uint32_t pad[30];
   uint32_t queue[RENDER_QUEUES][32];  // queue[q][0]: next position of queue q
 };
 static_assert(sizeof(FrameHeader) == 128 * (1 + RENDER_QUEUES), "frame header layout");
+static_assert(offsetof(FrameHeader, direct_count) == offsetof(FrameHeader, live_count) + 4, "64-bit counter pair");
 
 // header, live list (nb records), batch-order index of the live list (nb slots)
 inline uint64_t frame_area_bytes(uint64_t nb) { return sizeof(FrameHeader) + (sizeof(LiveBatch) + 4) * nb; }

@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
   uint32_t* const qc = &a.hdr->queue[q][0];
   // batch order (Morton order for sorted clouds): the sums' lines of neighbouring
   // batches stay in the caches; measured faster than the render's order here
-  const uint32_t n = a.hdr->order_count;
+  const uint32_t n = a.hdr->live_count + a.hdr->direct_count;
   if (tid == 0) {
     const uint32_t p = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
     s_next = p < n ? a.order[p] : ~0u;

@@ -63,7 +63,6 @@ __global__ void __launch_bounds__(256) k_clear(uint4* __restrict__ vb4, uint64_t
     if (hdr && threadIdx.x == 0) {
       hdr->live_count = 0;
       hdr->direct_count = 0;
-      hdr->order_count = 0;
     }
     if (hdr && threadIdx.x < RENDER_QUEUES) hdr->queue[threadIdx.x][0] = 0;
     if (reset_stats && threadIdx.x < 16) dev->stats[threadIdx.x] = 0;
@@ -262,23 +261,23 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
       }
     }
   }
-  // tiled batches from the front of the list, untiled ones from the back
+  // tiled batches from the front of the list, untiled ones from the back, and
+  // every live batch's slot into the batch-order index (for the shading
+  // pass): the wave's prefix there is the sum of its two list prefixes
   const bool tiled = live && ((out.mode >> 16) & 1u);
   const uint64_t mt = __ballot(tiled), md = __ballot(live && !tiled);
-  uint32_t bt = 0, bd = 0;
-  if (lane == 0 && mt) bt = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(mt));
-  if (lane == 0 && md) bd = atomicAdd(&a.hdr->direct_count, (uint32_t)__popcll(md));
-  bt = __shfl(bt, 0);
-  bd = __shfl(bd, 0);
+  uint64_t pre = 0;
+  if (lane == 0 && (mt | md))
+    pre = atomicAdd(reinterpret_cast<unsigned long long*>(&a.hdr->live_count),
+                    (unsigned long long)__popcll(mt) | ((unsigned long long)__popcll(md) << 32));
+  pre = __shfl(pre, 0);
+  const uint32_t bt = (uint32_t)pre, bd = (uint32_t)(pre >> 32);
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t slot = tiled ? bt + (uint32_t)__popcll(mt & lt) : a.nb - 1u - (bd + (uint32_t)__popcll(md & lt));
-  if (live) a.live[slot] = out;
-  // and the slots in batch order, for the shading pass
-  const uint64_t ml = __ballot(live);
-  uint32_t bo = 0;
-  if (lane == 0 && ml) bo = atomicAdd(&a.hdr->order_count, (uint32_t)__popcll(ml));
-  bo = __shfl(bo, 0);
-  if (live) a.order[bo + (uint32_t)__popcll(ml & lt)] = slot;
+  if (live) {
+    const uint32_t slot = tiled ? bt + (uint32_t)__popcll(mt & lt) : a.nb - 1u - (bd + (uint32_t)__popcll(md & lt));
+    a.live[slot] = out;
+    a.order[bt + bd + (uint32_t)__popcll((mt | md) & lt)] = slot;
+  }
 }
 
 // Several views: one thread per batch runs the prologue for each view of
@@ -336,11 +335,12 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
   }
   const bool live = mask != 0, direct = live && !tiled_any;
   const uint64_t mt = __ballot(live && !direct), md = __ballot(direct);
-  uint32_t bt = 0, bd = 0;
-  if (lane == 0 && mt) bt = atomicAdd(&a.hdr->live_count, (uint32_t)__popcll(mt));
-  if (lane == 0 && md) bd = atomicAdd(&a.hdr->direct_count, (uint32_t)__popcll(md));
-  bt = __shfl(bt, 0);
-  bd = __shfl(bd, 0);
+  uint64_t pre = 0;
+  if (lane == 0 && (mt | md))
+    pre = atomicAdd(reinterpret_cast<unsigned long long*>(&a.hdr->live_count),
+                    (unsigned long long)__popcll(mt) | ((unsigned long long)__popcll(md) << 32));
+  pre = __shfl(pre, 0);
+  const uint32_t bt = (uint32_t)pre, bd = (uint32_t)(pre >> 32);
   if (live) {
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     Run r;
