@@ -344,6 +344,28 @@ def lod_leg(pr, ctx, n: int, steps: int, warmup: int):
                                             "gpts": round(processed / (t * 1e-3) / 1e9, 3),
                                             "all_points_rate_gpts": round(n * len(cams) / (t * 1e-3) / 1e9, 3)}
         res["frame_speedup"] = round(res["lod_px_0"]["ms_per_frame"] / res["lod_px_100"]["ms_per_frame"], 3)
+        # the autotuner on the LOD frame (lod_px 100): winner, then the same plain frame under it
+        need = pr.pr_views_work_bytes(dc.handle, len(cams))
+        work = torch.empty(need, dtype=torch.uint8, device="cuda")
+        best, trials = pr.pr_autotune(ctx.handle, dc.handle, [(c.view, c.proj, c.width, c.height, vb)
+                                                              for c, vb in zip(cams, vbs)],
+                                      pr.RenderOpts.make(lod_px=100.0), work, need, 3)
+        o = pr.RenderOpts.make(lod_px=100.0)
+        for _ in range(warmup):
+            step()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            step()
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        res["lod_px_100_tuned"] = {"tuning": best, "shape": pr.pr_raster_shapes(ctx.handle)[best["shape"]],
+                                   "ms_per_frame": round(t, 4),
+                                   "speedup_vs_default": round(res["lod_px_100"]["ms_per_frame"] / t, 3)}
+        pr.pr_set_tuning(ctx.handle)
+        del work
         out[vname] = res
         log(f"lod {vname}: {res}")
     pr.pr_sync(ctx.handle)
