@@ -23,7 +23,6 @@ so the merge is exact.
 """
 from __future__ import annotations
 
-import time
 import types
 from concurrent.futures import ThreadPoolExecutor
 
@@ -31,26 +30,10 @@ import numpy as np
 import pytest
 
 import oracle
-import synth
+from fullsize_util import CH, CLEAR, RENDER_WORKERS, S, _t, _u32, check_morton_build, device_views, oracle_frame
 from gpu_util import assert_vb_equal, oracle_stats_match, say
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
-
-S = 10240
-CLEAR = 0xFF000000
-CH = 64_000_000  # host chunk: 6250 whole batches
-WORKERS = 4      # build-check workers, each generator call on 4 threads: 16 host threads, the GPU host's share
-RENDER_WORKERS = 16
-
-
-def _t():
-    return time.perf_counter()
-
-
-def _u32(t):
-    """A torch int32 tensor (device) as a host numpy uint32 array."""
-    return t.cpu().numpy().view(np.uint32)
-
 
 @pytest.fixture(scope="module")
 def ctx():
@@ -61,17 +44,6 @@ def ctx():
     c = pr.Context(0)
     yield c
     c.close()
-
-
-def _views(cloud, n, nb):
-    import torch
-
-    m = cloud["mem"]
-    return types.SimpleNamespace(
-        xyz=m["xyz"][: 12 * n].view(torch.int32), perm=m["perm"][: 4 * n].view(torch.int32),
-        colors=m["colors"][: 4 * n].view(torch.int32), low=m["low"][: 4 * n].view(torch.int32),
-        med=m["med"][: 4 * n].view(torch.int32), high=m["high"][: 4 * n].view(torch.int32),
-        batches=m["batches"][: 32 * nb])
 
 
 def _bench_frame(ctx, handle, cam):
@@ -94,33 +66,12 @@ def _bench_frame(ctx, handle, cam):
     return out_vb, out_fb, st
 
 
-def _oracle_frame(built, cam, nb):
-    """The oracle over every batch, on worker threads (interleaved batch sets, private buffers, min-merge)."""
-    groups = [np.arange(g, nb, 4 * RENDER_WORKERS, dtype=np.uint64) for g in range(min(nb, 4 * RENDER_WORKERS))]
-
-    def job(ids):
-        return oracle.render(built, cam.view, cam.proj, cam.width, cam.height, batch_ids=ids)
-
-    vb, st = None, None
-    with ThreadPoolExecutor(RENDER_WORKERS) as ex:
-        for v, s in ex.map(job, groups):
-            vb = v if vb is None else np.minimum(vb, v)
-            if st is None:
-                st = s
-            else:
-                for k in ("batches", "culled", "points"):
-                    st[k] += s[k]
-                for k in ("level_batches", "level_points"):
-                    st[k] = [a + b for a, b in zip(st[k], s[k])]
-    return vb, st
-
-
 def _check_eye(ctx, handle, built, colors, cam, nb, tag):
     t0 = _t()
     say(f"{tag}: bench frame on the GPU ({cam.width}x{cam.height})")
     vb, fb, st = _bench_frame(ctx, handle, cam)
     say(f"{tag}: GPU frame done ({_t() - t0:.1f} s); oracle render of {nb} batches on {RENDER_WORKERS} threads")
-    ref, st_ref = _oracle_frame(built, cam, nb)
+    ref, st_ref = oracle_frame(built, cam, nb)
     say(f"{tag}: oracle done ({_t() - t0:.1f} s): {st_ref}")
     assert_vb_equal(vb, ref, cam.width)
     assert np.array_equal(fb, oracle.resolve(ref, colors, CLEAR)), "framebuffer differs"
@@ -157,7 +108,7 @@ def c2(ctx):
 def test_c2_build_full(c2):
     n, nb, B = c2.n, c2.nb, c2.B
     assert nb == B.batches.shape[0]
-    v = _views(c2.cloud, n, nb)
+    v = device_views(c2.cloud, n, nb)
     say("C2: compare every build output with the oracle")
     for f in ("perm", "colors", "low", "med", "high"):
         a = _u32(getattr(v, f))
@@ -176,63 +127,6 @@ def test_c2_orbit_frame(ctx, c2, frame):
 
 
 # =================================================================== C3: 2e9
-def _c3_oracle_side(ns):
-    """Check the device's Morton build against the oracle over all 2e9 points; keep the oracle's build."""
-    import torch
-
-    n, nb, seed = ns.n, ns.nb, ns.wl["seed"]
-    v = _views(ns.cloud, n, nb)
-    t0 = _t()
-    # 1. perm is a permutation of 0..n-1 (bounds first: an out-of-range index must not reach the GPU)
-    say("C3: permutation check on the device")
-    marks = torch.zeros(n, dtype=torch.uint8, device=v.perm.device)
-    for lo in range(0, n, CH):
-        idx = v.perm[lo:min(n, lo + CH)].to(torch.int64) & 0xFFFFFFFF
-        assert int(idx.max()) < n, "perm holds an index >= n"
-        marks[idx] = 1
-    assert int(marks.min()) == 1, "perm is not a permutation"
-    del marks, idx
-    torch.cuda.synchronize()
-    say(f"C3: permutation ok ({_t() - t0:.1f} s); chunked pass over the build")
-    # 2. chunked pass: generator points in device order -> oracle codes, batches, words; compare
-    cmin, cmax = ns.cloud_box
-    built = types.SimpleNamespace(batches=np.empty(nb, oracle.BATCH_DTYPE), low=np.empty(n, np.uint32),
-                                  med=np.empty(n, np.uint32), high=np.empty(n, np.uint32))
-    colors = np.empty(n, np.uint32)
-    gb_all = v.batches.cpu().numpy()
-
-    def job(lo):
-        hi = min(n, lo + CH)
-        perm = _u32(v.perm[lo:hi])
-        ox, oc = synth.terrain_gather(seed, n, perm, threads=4)
-        codes = oracle.morton_codes(ox, cmin, cmax)
-        tie = codes[1:] == codes[:-1]
-        r = dict(lo=lo, mono=bool(np.all(codes[1:] >= codes[:-1])), stable=bool(np.all(perm[1:][tie] > perm[:-1][tie])),
-                 head=(int(codes[0]), int(perm[0])), tail=(int(codes[-1]), int(perm[-1])))
-        r["xyz"] = bool(np.array_equal(_u32(v.xyz[3 * lo:3 * hi]), ox.view(np.uint32).reshape(-1)))
-        r["colors"] = bool(np.array_equal(_u32(v.colors[lo:hi]), oc))
-        ob = oracle.make_batches(ox, S)
-        words = oracle.quantize(ox, ob)
-        for f, w in zip(("low", "med", "high"), words):
-            r[f] = bool(np.array_equal(_u32(getattr(v, f)[lo:hi]), w))
-            getattr(built, f)[lo:hi] = w
-        ob["first"] += np.uint32(lo)
-        b0 = lo // S
-        r["batches"] = bool(np.array_equal(gb_all[32 * b0:32 * (b0 + len(ob))], ob.view(np.uint8)))
-        built.batches[b0:b0 + len(ob)] = ob
-        colors[lo:hi] = oc
-        return r
-
-    with ThreadPoolExecutor(WORKERS) as ex:
-        res = []
-        for r in ex.map(job, range(0, n, CH)):
-            res.append(r)
-            if len(res) % 8 == 0:
-                say(f"C3: {len(res)} chunks checked ({_t() - t0:.1f} s)")
-    say(f"C3: chunked pass done ({_t() - t0:.1f} s)")
-    return res, built, colors
-
-
 @pytest.fixture(scope="module")
 def c3(ctx):
     import torch
@@ -252,7 +146,7 @@ def c3(ctx):
     pool.shutdown()
     corners = np.array([c for f in boxes for c in f.result()], np.float32)
     ns = types.SimpleNamespace(wl=wl, cloud=cloud, n=wl["n"], nb=cloud["nb"], cloud_box=oracle.cloud_aabb(corners))
-    ns.res, ns.built, ns.colors = _c3_oracle_side(ns)
+    ns.res, ns.built, ns.colors = check_morton_build(ns, "C3")
     yield ns
     import paper_2204_01287_amd as pr
 
@@ -295,7 +189,7 @@ def test_c3_stereo_one_launch(ctx, c3):
     pr.pr_sync(ctx.handle)
     tot = None
     for c, vb in zip(cams, vbs):
-        ref, s = _oracle_frame(c3.built, c, c3.nb)
+        ref, s = oracle_frame(c3.built, c, c3.nb)
         assert_vb_equal(vb.cpu().numpy().view(np.uint64), ref, c.width)
         tot = s if tot is None else {k: (tot[k] + s[k] if not isinstance(s[k], list) else
                                          [a + b for a, b in zip(tot[k], s[k])]) for k in s}
@@ -316,7 +210,7 @@ def test_c3_hqs_eye0(ctx, c3):
     say("C3: high-quality shading of eye 0")
     pr.pr_render_hqs(ctx.handle, c3.cloud["handle"], cam.view, cam.proj, w, h, None, 1.01, vb, acc, CLEAR, fb)
     pr.pr_sync(ctx.handle)
-    ref, _ = _oracle_frame(c3.built, cam, c3.nb)
+    ref, _ = oracle_frame(c3.built, cam, c3.nb)
     assert_vb_equal(vb.cpu().numpy().view(np.uint64), ref, w)
     groups = [np.arange(g, c3.nb, 4 * RENDER_WORKERS, dtype=np.uint64) for g in range(4 * RENDER_WORKERS)]
 
