@@ -4,11 +4,13 @@ A request names a resident cloud, a camera and an image size, and arrives at som
 
   * admits arrived requests in arrival order while the bytes of their visibility buffer and framebuffer
     (12 bytes per pixel) fit the memory budget (a request larger than the whole budget runs alone);
-  * groups the admitted requests that are not yet on the GPU by cloud and renders each group with one
-    pr_render_views launch (at most PR_MAX_VIEWS views; the batches' coordinate words are streamed once for the
-    whole group) followed by one resolve per view;
-  * issues each group on the least-loaded of several HIP streams (one library context per stream), so that work
-    for different clouds overlaps on the device, and requests that arrive while others run join the next pass;
+  * keeps the admitted requests that are not yet on the GPU per cloud, and whenever a HIP stream has fewer than
+    `depth` groups in flight, launches the cloud with the oldest waiting request as one group on it: one
+    pr_render_views launch for up to PR_MAX_VIEWS of that cloud's waiting requests (the batches' coordinate words
+    are streamed once for the whole group) followed by one resolve per view;
+  * runs several streams (one library context each), so that groups of different clouds overlap on the device;
+    requests that arrive while the streams are busy wait and join larger groups, and at low load a stream is
+    always free, so a request is launched as soon as it is admitted;
   * retires a group when its event has passed: hands each result to the caller's callback, frees its memory.
 
 Latency = completion (host clock when the group's event is seen complete) - arrival.  Every result equals the
@@ -50,11 +52,14 @@ class Server:
     """Renders requests against resident, built clouds (DeviceCloud or handles) on one device."""
 
     def __init__(self, clouds, device: int = 0, nstreams: int = 4, budget_bytes: int = 4 << 30,
-                 max_group: int = B.PR_MAX_VIEWS, clear_rgba: int = 0xFF000000, on_result=None):
+                 max_group: int = B.PR_MAX_VIEWS, clear_rgba: int = 0xFF000000, on_result=None, depth: int = 1):
         import torch
 
         if not 1 <= max_group <= B.PR_MAX_VIEWS:
             raise ValueError("max_group must be in 1..PR_MAX_VIEWS")
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
+        self.depth = depth  # groups in flight per stream
         self.torch = torch
         self.device = device
         self.handles = [getattr(c, "handle", c) for c in clouds]
@@ -91,7 +96,8 @@ class Server:
     def run(self, requests, idle_sleep: float = 0.0):
         """Serve every request (arrival times relative to the call); returns a list of Done in completion order."""
         reqs = sorted(requests, key=lambda r: r.arrival)
-        pending: deque = deque()
+        pending: deque = deque()  # arrived, not admitted
+        waiting = {}  # cloud -> deque of admitted requests not yet on the GPU
         inflight = []  # [event, stream, group, vbs, fbs, work, bytes, launched]
         load = [0] * len(self.streams)
         done = []
@@ -121,24 +127,29 @@ class Server:
             admitted = []
             while pending:
                 nbytes = self.request_bytes(pending[0])
-                if used + nbytes > self.budget and (inflight or admitted):
+                if used + nbytes > self.budget and (inflight or admitted or waiting):
                     break
                 used += nbytes
                 admitted.append(pending.popleft())
             self.peak_bytes = max(self.peak_bytes, used)
-            groups = {}
             for r in admitted:
-                groups.setdefault(r.cloud, []).append(r)
-            for cloud, rs in groups.items():
-                for k in range(0, len(rs), self.max_group):
-                    group = rs[k:k + self.max_group]
-                    si = min(range(len(self.streams)), key=lambda i: load[i])
-                    launched = time.perf_counter() - t0
-                    ev, vbs, fbs, work = self._launch(si, cloud, group)
-                    inflight.append([ev, si, group, vbs, fbs, work, sum(self.request_bytes(r) for r in group),
-                                     launched])
-                    load[si] += 1
-            if not admitted and not retired:
+                waiting.setdefault(r.cloud, deque()).append(r)
+            launched_any = False
+            while waiting:
+                si = min(range(len(self.streams)), key=lambda i: load[i])
+                if load[si] >= self.depth:
+                    break
+                cloud = min(waiting, key=lambda c: waiting[c][0].arrival)
+                q = waiting[cloud]
+                group = [q.popleft() for _ in range(min(self.max_group, len(q)))]
+                if not q:
+                    del waiting[cloud]
+                launched = time.perf_counter() - t0
+                ev, vbs, fbs, work = self._launch(si, cloud, group)
+                inflight.append([ev, si, group, vbs, fbs, work, sum(self.request_bytes(r) for r in group), launched])
+                load[si] += 1
+                launched_any = True
+            if not admitted and not retired and not launched_any:
                 if idle_sleep:
                     time.sleep(idle_sleep)
         for ctx in self.ctxs:
