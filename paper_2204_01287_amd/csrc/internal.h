@@ -177,13 +177,14 @@ PR_RASTER_SHAPES(PR_DECLARE_SHAPE)
 
 hipError_t launch_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint64_t ncolors,
                           uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
-// high-quality shading: zero the sums, the shading pass over the live batches of
-// the last launch_render, the averaging resolve
+// high-quality shading (kern_accum.hip): zero the sums, the shading pass over
+// the live batches of the last classify + render, the averaging resolve
 hipError_t launch_accumulate(const RenderArgs& a, hipStream_t s);
 uint32_t accum_grid(int device);
 hipError_t launch_resolve_hqs(const uint64_t* accum, uint64_t npix, uint32_t clear_rgba, uint32_t* fb, hipStream_t s);
 
-// ---- HBM streaming probes (kern_stream.hip): copy src -> dst, or (dst null) read src, XOR into *sink
+// ---- HBM streaming probes (kern_stream.hip): copy src -> dst, or (dst null) only read src (sink: a marker
+// store that keeps the loads)
 hipError_t launch_stream(const void* src, void* dst, uint64_t bytes, uint64_t* sink, uint32_t blocks, hipStream_t s);
 
 // ---- load-time build (kern_build.hip)
