@@ -400,7 +400,7 @@ def autotune_leg(pr, ctx, cloud, cams, vbs, frame, plain_ms, steps, warmup):
     ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     pr.pr_set_tuning(ctx.handle)
     shapes = pr.pr_raster_shapes(ctx.handle)
-    default_ms = next(m for t, m in trials if t == {"shape": 0, "tile_px": 0, "wg_per_cu": 0})
+    default_ms = next(m for t, m in trials if t == {"shape": 0, "tile_px": 0, "wg_per_cu": 0, "max_bands": 0})
     res = {"candidates": len(trials), "tune_s": round(t_tune, 2), "best": best, "best_shape": shapes[best["shape"]],
            "multiview_frame_ms": {"default": round(default_ms, 4), "best": round(min(m for _, m in trials), 4)},
            "plain_step_ms": {"default": round(plain_ms, 4), "tuned": round(ms, 4)},
@@ -464,7 +464,7 @@ def camera_array_leg(pr, ctx, n: int, steps: int, warmup: int, sizes=(5120, 1024
 
     out = {"points": n, "views": "64 x 1024x1024", "tune_s": round(t_tune, 1), "candidates": len(res["trials"]),
            "best": best, "best_shape": pr.pr_raster_shapes(ctx.handle)[best["tuning"]["shape"]]}
-    configs = {"default": (10240, {"shape": 0, "tile_px": 0, "wg_per_cu": 0}),
+    configs = {"default": (10240, {"shape": 0, "tile_px": 0, "wg_per_cu": 0, "max_bands": 0}),
                "tuned": (best["batch_size"], best["tuning"])}
     for name, (S, t) in configs.items():
         c = kept[S]

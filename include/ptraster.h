@@ -287,7 +287,9 @@ typedef struct {
   uint32_t tile_px;   /* largest batch rectangle combined in LDS, at most the shape's tile;
                          0 = the shape's tile [0]                                           */
   uint32_t wg_per_cu; /* persistent workgroups per CU, at most what fits; 0 = all that fit [0] */
-  uint32_t reserved;  /* must be 0                                                          */
+  uint32_t max_bands; /* a 10-bit batch larger than the tile bound, at most one tile wide and
+                         at most max_bands tiles large, renders in bands of rows through
+                         the LDS tile (1 = never, at most 64); 0 = 4 [0]                    */
 } pr_tuning;
 
 /* The compiled shapes in index order (shape 0 is the default): writes
@@ -298,7 +300,7 @@ pr_status pr_raster_shapes(const pr_ctx* ctx, pr_raster_shape* out, uint32_t cap
 /* Set the context's tuning (NULL: the default {0, 0, 0, 0}); later frames on
  * this context use it.  Not for a context with frames being enqueued from
  * another thread.  PR_EINVAL for an unknown shape, tile_px above the
- * shape's tile, wg_per_cu above what fits, or reserved != 0. */
+ * shape's tile, wg_per_cu above what fits, or max_bands above 64. */
 pr_status pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
 pr_status pr_get_tuning(const pr_ctx* ctx, pr_tuning* out);
 
@@ -310,13 +312,14 @@ typedef struct {
 } pr_tune_trial;
 
 /* Autotuner: times pr_render_views(ctx, cloud, views, nviews, opts, work,
- * work_bytes) under each candidate tuning (every shape, its full and half
- * tile bound, all and half of the workgroups that fit), one untimed frame
- * then reps timed frames each (reps 0 = 3), and sets the context's tuning to
- * the fastest (the first of equal times).  The candidates' trials go to
- * trials (host, first min(cap, total) in candidate order; may be NULL when
- * cap is 0), their number to *ntrials, the winner to *best (may be NULL).
- * Afterwards every view's visibility buffer holds the frame.  Synchronises.
+ * work_bytes) under each candidate tuning, one untimed frame then reps timed
+ * frames each (reps 0 = 3), and sets the context's tuning to the fastest (the
+ * first of equal times).  Candidates: every shape with its full and half tile
+ * bound and all or half of the workgroups that fit (band limit 4); then the
+ * winner with band limits 1, 2, 8 and 16.  The trials go to trials (host,
+ * first min(cap, total) in candidate order; may be NULL when cap is 0), their
+ * number to *ntrials, the winner to *best (may be NULL).  Afterwards every
+ * view's visibility buffer holds the frame.  Synchronises.
  * opts->accumulate and opts->counters must be 0 (PR_EINVAL); other errors as
  * pr_render_views.  On an error the context's tuning is left unchanged. */
 pr_status pr_autotune(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,

@@ -77,10 +77,10 @@ class RasterShape(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_uint32), ("tile_px", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("max_bands", ctypes.c_uint32)]
 
     def as_dict(self):
-        return {"shape": self.shape, "tile_px": self.tile_px, "wg_per_cu": self.wg_per_cu}
+        return {"shape": self.shape, "tile_px": self.tile_px, "wg_per_cu": self.wg_per_cu, "max_bands": self.max_bands}
 
 
 class TuneTrial(ctypes.Structure):
@@ -268,8 +268,8 @@ def pr_raster_shapes(ctx) -> list:
     return [a.as_dict() for a in arr]
 
 
-def pr_set_tuning(ctx, shape: int = 0, tile_px: int = 0, wg_per_cu: int = 0, reserved: int = 0):
-    t = Tuning(shape, tile_px, wg_per_cu, reserved)
+def pr_set_tuning(ctx, shape: int = 0, tile_px: int = 0, wg_per_cu: int = 0, max_bands: int = 0):
+    t = Tuning(shape, tile_px, wg_per_cu, max_bands)
     _check(lib.pr_set_tuning(ctx, ctypes.byref(t)), "pr_set_tuning")
 
 

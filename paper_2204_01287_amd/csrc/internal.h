@@ -32,7 +32,7 @@ enum { ST_BATCHES = 0, ST_CULLED, ST_POINTS, ST_LB0, ST_LB1, ST_LB2, ST_LP0, ST_
 // (written by the classify kernel, read with scalar loads by the render kernel).
 struct LiveBatch {
   uint32_t first, count;
-  uint32_t mode;     // level (10, 20, 30) | class << 8 | tiled << 16
+  uint32_t mode;     // level (10, 20, 30) | class << 8 | tiled << 16 | banded << 17
   uint32_t rect_xy;  // tile rectangle origin: x0 | y0 << 16
   uint32_t rect_wh;  // tile rectangle size: tw | th << 16
   float P[3][3];     // folded per-batch matrix (binary32)
@@ -48,6 +48,10 @@ static_assert(sizeof(LiveBatch) == 80, "live batch record is 80 bytes");
 // A position maps to a live-list slot with the untiled batches spread evenly
 // among the tiled ones (live_slot in raster_core.h).
 constexpr uint32_t RENDER_QUEUES = 8;
+// A 10-bit batch whose tile rectangle exceeds the tile but is at most one
+// tile wide and max_bands tiles large is rendered in bands of rows that fit
+// the tile (max_bands: a tuning; 1 = no bands).
+constexpr uint32_t DEFAULT_BANDS = 4, MAX_BANDS = 64;
 struct FrameHeader {
   // One 64-bit counter (classify adds tiled | untiled << 32 with one atomic
   // per wave, so the two prefixes it returns come from one order):
@@ -78,6 +82,7 @@ struct RenderArgs {
   float t10, t20;
   uint32_t grid;    // persistent render workgroups
   uint32_t tile_max;     // classify: largest rectangle (pixels) a tiled batch may cover
+  uint32_t max_bands;    // classify: largest rectangle of a banded batch, in tiles
   const LodNode* nodes;  // LOD layouts: node per batch (else nullptr)
   float lod_px;          // > 0: cull nodes below the root whose cube projects below lod_px pixels
   // high-quality shading pass only
@@ -116,7 +121,7 @@ struct ClassifyViewsArgs {
   float t10, t20;
   const LodNode* nodes;
   float lod_px;
-  uint32_t tile_max;
+  uint32_t tile_max, max_bands;
   uint32_t cap;  // run slots (one per batch and classify launch)
   ViewIn v[VIEW_CHUNK];
 };

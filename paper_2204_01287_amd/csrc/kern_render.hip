@@ -108,11 +108,12 @@ __device__ __forceinline__ double cube_extent(const double (&Pm)[3][4], const Lo
 
 // node: the batch's LOD node or nullptr.  LOD culling (Sec. 3.5): with
 // lod_px > 0, a batch of a node below the root is culled iff its node's cube
-// projects to less than lod_px pixels.  tile_max: the most pixels a tiled
+// projects to less than lod_px pixels.  max_bands: see below.  tile_max: the most pixels a tiled
 // batch's rectangle may cover (the render kernel's LDS tile or less).
 __device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (&Pm)[3][4], uint32_t W, uint32_t Hh,
                                              int32_t precision, int32_t cull, float t10, float t20,
-                                             const LodNode* node, float lod_px, uint32_t tile_max, LiveBatch& out,
+                                             const LodNode* node, float lod_px, uint32_t tile_max,
+                                             uint32_t max_bands, LiveBatch& out,
                                              bool& culled, int& li) {
   bool live = false;
   double H[3][8], M[3];
@@ -177,7 +178,7 @@ __device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (
     // lies inside it when the binary32 evaluation (hx, hw off by at most
     // M/16 each) moves its quotient by less than half a pixel:
     //   (Mx + max|u| Mw) / 16 / (min_c hw - Mw) < 1/2, and likewise for y.
-    uint32_t tiled = 0, x0 = 0, y0 = 0, tw = 0, th = 0;
+    uint32_t tiled = 0, banded = 0, x0 = 0, y0 = 0, tw = 0, th = 0;
     double hwmin = H[2][0];
 #pragma unroll
     for (int c = 1; c < 8; ++c) hwmin = fmin(hwmin, H[2][c]);
@@ -190,8 +191,13 @@ __device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (
       const double fx1 = fmin(floor(fmin(umax, Wd + 4.0)) + 1.0, Wd - 1.0);
       const double fy0 = fmax(floor(fmax(vmin, -4.0)) - 1.0, 0.0);
       const double fy1 = fmin(floor(fmin(vmax, Hd + 4.0)) + 1.0, Hd - 1.0);
-      if (fx1 >= fx0 && fy1 >= fy0 && (fx1 - fx0 + 1.0) * (fy1 - fy0 + 1.0) <= (double)tile_max) {
-        tiled = 1;
+      const double rw = fx1 - fx0 + 1.0, area = rw * (fy1 - fy0 + 1.0);
+      if (fx1 >= fx0 && fy1 >= fy0 && area <= (double)tile_max) tiled = 1;
+      // larger, but at most max_bands tiles and one tile wide, at 10 bits: rendered band by band
+      else if (k == 10 && max_bands > 1 && fx1 >= fx0 && fy1 >= fy0 && rw <= (double)tile_max &&
+               area <= (double)max_bands * (double)tile_max)
+        banded = 1;
+      if (tiled || banded) {
         x0 = (uint32_t)fx0;
         y0 = (uint32_t)fy0;
         tw = (uint32_t)(fx1 - fx0) + 1u;
@@ -209,7 +215,7 @@ __device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (
     }
     out.first = rec.first;
     out.count = rec.count;
-    out.mode = (uint32_t)k | ((uint32_t)cls << 8) | (tiled << 16);
+    out.mode = (uint32_t)k | ((uint32_t)cls << 8) | (tiled << 16) | (banded << 17);
     out.rect_xy = x0 | (y0 << 16);
     out.rect_wh = tw | (th << 16);
     out.pad[0] = out.pad[1] = out.pad[2] = 0;
@@ -235,7 +241,7 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
     const BatchRec rec = a.batches[b];
     count = rec.count;
     live = decide_batch(rec, a.Pm, a.W, a.H, a.precision, a.cull, a.t10, a.t20, a.nodes ? a.nodes + b : nullptr,
-                        a.lod_px, a.tile_max, out, culled, li);
+                        a.lod_px, a.tile_max, a.max_bands, out, culled, li);
   }
   if constexpr (CNT) {
     const uint64_t mv = __ballot(valid), mc = __ballot(valid && culled);
@@ -299,7 +305,7 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
       bool culled = false;
       int li = 0;
       if (decide_batch(rec, a.v[v].Pm, a.v[v].W, a.v[v].H, a.precision, a.cull, a.t10, a.t20,
-                       a.nodes ? a.nodes + b : nullptr, a.lod_px, a.tile_max, out, culled, li)) {
+                       a.nodes ? a.nodes + b : nullptr, a.lod_px, a.tile_max, a.max_bands, out, culled, li)) {
         a.sub[(uint64_t)b * a.nviews + a.view0 + v] = out;
         mask |= 1ull << v;
         tiled_any = tiled_any || ((out.mode >> 16) & 1u);

@@ -102,6 +102,7 @@ uint32_t shape_tile(const pr_tuning& t) {
   const uint32_t full = shape_of(t).tile;
   return t.tile_px && t.tile_px < full ? t.tile_px : full;
 }
+uint32_t tune_bands(const pr_tuning& t) { return t.max_bands ? t.max_bands : ptr::DEFAULT_BANDS; }
 uint32_t shape_grid(const pr_ctx* ctx, const pr_tuning& t, int views) {
   uint32_t per = ctx->per_cu[t.shape][views];
   if (t.wg_per_cu && t.wg_per_cu < per) per = t.wg_per_cu;
@@ -432,6 +433,7 @@ pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16],
   const pr_tuning tune = ctx->tuning;
   a.grid = shape_grid(ctx, tune, 0);
   a.tile_max = shape_tile(tune);
+  a.max_bands = tune_bands(tune);
   a.vb = visbuf;
   a.stats = ctx->dev->stats;
   frame_matrix(view, proj, w, h, a.Pm);
@@ -564,6 +566,7 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
     k.nodes = cloud->lod ? static_cast<const ptr::LodNode*>(cloud->bufs.nodes) : nullptr;
     k.lod_px = o.lod_px;
     k.tile_max = shape_tile(tune);
+    k.max_bands = tune_bands(tune);
     k.cap = (uint32_t)(nb * nchunks);
     for (uint32_t v = 0; v < k.nchunk; ++v) {
       const pr_view& pv = views[k.view0 + v];
@@ -676,7 +679,8 @@ pr_status pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning) {
   const uint32_t fit = ctx->per_cu[t.shape][0] > ctx->per_cu[t.shape][1] ? ctx->per_cu[t.shape][0]
                                                                           : ctx->per_cu[t.shape][1];
   if (t.wg_per_cu > fit) return fail(PR_EINVAL, "pr_set_tuning: wg_per_cu %u above the %u that fit", t.wg_per_cu, fit);
-  if (t.reserved) return fail(PR_EINVAL, "pr_set_tuning: reserved must be 0");
+  if (t.max_bands > ptr::MAX_BANDS)
+    return fail(PR_EINVAL, "pr_set_tuning: max_bands %u above %u", t.max_bands, ptr::MAX_BANDS);
   ctx->tuning = t;
   return PR_OK;
 }
@@ -695,42 +699,49 @@ pr_status pr_autotune(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, 
     return fail(PR_EINVAL, "pr_autotune: accumulate and counters must be 0");
   if (pr_status s = set_device(ctx)) return s;
   if (reps == 0) reps = 3;
-  std::vector<pr_tuning> cand;
-  for (uint32_t i = 0; i < kNumShapes; ++i) {
-    const uint32_t fit = ctx->per_cu[i][1];
-    for (uint32_t tile : {0u, shape_at(i).tile / 2})
-      for (uint32_t wg : {0u, fit / 2})
-        if (wg == 0 || wg < fit) cand.push_back({i, tile, wg, 0});
-  }
   const pr_tuning saved = ctx->tuning;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   pr_status st = PR_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(PR_EDEVICE, "pr_autotune: events");
+  uint32_t n = 0;
   float best_ms = 0.0f;
   pr_tuning win = saved;
-  for (size_t c = 0; c < cand.size() && st == PR_OK; ++c) {
-    ctx->tuning = cand[c];
-    st = pr_render_views(ctx, cloud, views, nviews, opts, work, work_bytes);  // untimed: caches, clocks
+  // one candidate: an untimed frame (caches, clocks), then reps timed frames
+  auto trial = [&](const pr_tuning& t) {
+    if (st != PR_OK) return;
+    ctx->tuning = t;
+    st = pr_render_views(ctx, cloud, views, nviews, opts, work, work_bytes);
     hipError_t e = hipSuccess;
     if (st == PR_OK) e = hipEventRecord(e0, ctx->stream);
     for (uint32_t r = 0; r < reps && st == PR_OK && e == hipSuccess; ++r)
       st = pr_render_views(ctx, cloud, views, nviews, opts, work, work_bytes);
-    if (st != PR_OK) break;
+    if (st != PR_OK) return;
     if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) {
       st = hip_fail(e, "pr_autotune: timing");
-      break;
+      return;
     }
     ms /= (float)reps;
-    if (c < cap) trials[c] = {cand[c], ms, 0};
-    if (c == 0 || ms < best_ms) {
+    if (n < cap) trials[n] = {t, ms, 0};
+    if (n == 0 || ms < best_ms) {
       best_ms = ms;
-      win = cand[c];
+      win = t;
     }
+    ++n;
+  };
+  // stage 1: every shape with its full and half tile bound, all and half the workgroups that fit
+  for (uint32_t i = 0; i < kNumShapes; ++i) {
+    const uint32_t fit = ctx->per_cu[i][1];
+    for (uint32_t tile : {0u, shape_at(i).tile / 2})
+      for (uint32_t wg : {0u, fit / 2})
+        if (wg == 0 || wg < fit) trial({i, tile, wg, 0});
   }
+  // stage 2: the band limit for the winner of stage 1
+  const pr_tuning w1 = win;
+  for (uint32_t bands : {1u, 2u, 8u, 16u}) trial({w1.shape, w1.tile_px, w1.wg_per_cu, bands});
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (st != PR_OK) {
@@ -738,7 +749,7 @@ pr_status pr_autotune(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, 
     return st;
   }
   ctx->tuning = win;
-  *ntrials = (uint32_t)cand.size();
+  *ntrials = n;
   if (best) *best = win;
   return PR_OK;
 }

@@ -169,7 +169,10 @@ __device__ __forceinline__ void four_points_acc(const Loop& L, uint64_t* tile, c
 }
 
 // Four consecutive points of one lane.
-template <int K, int CLS, bool TILED, bool ACC = false>
+// BAND (tiled path only): the tile covers one band of rows of the batch's
+// rectangle (L.th rows from the band origin); points of other rows are
+// skipped (their tile row, taken as unsigned, is >= L.th).
+template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
 __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const Words& w, uint32_t i0,
                                             uint32_t nvalid, uint32_t& natom) {
   if constexpr (ACC) {
@@ -201,12 +204,13 @@ __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const
       if constexpr (CLS != CLS_INSIDE) ok[j] = ok[j] && visible(L, p);
       uint32_t lx, ly;
       pixel_fast(p, L.cx, L.cy, lx, ly);
+      if constexpr (BAND) ok[j] = ok[j] && (ly < L.th);
       key[j] = make_key(p.hw, i0 + j);
       ad[j] = __umul24(ly, L.tw8) + (lx << 3);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if constexpr (CLS == CLS_INSIDE) {
+      if constexpr (CLS == CLS_INSIDE && !BAND) {
         // Every point of an INSIDE batch box (padding lanes decode to points
         // of the box too) maps into the tile: the read needs no guard.
         old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
@@ -285,7 +289,7 @@ __device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, ui
 // The points of one batch, split over the workgroup's waves: wave w takes the
 // groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
 // 16-byte load per word).  Wave 0 also takes the ragged tail.
-template <int K, int CLS, bool TILED, bool ACC = false>
+template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
 __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
                               uint32_t wave, uint32_t lane, uint32_t& natom) {
   const uint32_t ngrp = count >> 8;
@@ -313,7 +317,7 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
 #pragma unroll
       for (int d = 0; d < PREFETCH; ++d) {
         const uint32_t g = gi[d];
-        four_points<K, CLS, TILED, ACC>(L, tile, R[d], first + min(g, glast) * 256 + lane * 4,
+        four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + min(g, glast) * 256 + lane * 4,
                                         g <= glast ? 4u : 0u, natom);
         gi[d] = g + PREFETCH * WAVES;
         R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
@@ -339,7 +343,7 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
     t.m = make_uint4(m[0], m[1], m[2], m[3]);
     t.h = make_uint4(h[0], h[1], h[2], h[3]);
     t.c = make_uint4(c[0], c[1], c[2], c[3]);
-    four_points<K, CLS, TILED, ACC>(L, tile, t, first + j0, nv, natom);
+    four_points<K, CLS, TILED, ACC, BAND>(L, tile, t, first + j0, nv, natom);
   }
 }
 
@@ -355,24 +359,44 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
 
 
 // ------------------------------------------------------------------ render
-template <int K, bool TILED, bool ACC = false>
+template <int K, bool TILED, bool ACC = false, bool BAND = false>
 __device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const Streams& a, uint64_t* tile,
                                                 uint32_t first, uint32_t count, uint32_t wave, uint32_t lane,
                                                 uint32_t& natom) {
   if (cls == CLS_INSIDE)
-    raster_points<K, CLS_INSIDE, TILED, ACC>(L, a, tile, first, count, wave, lane, natom);
+    raster_points<K, CLS_INSIDE, TILED, ACC, BAND>(L, a, tile, first, count, wave, lane, natom);
   else if (cls == CLS_PARTIAL)
-    raster_points<K, CLS_PARTIAL, TILED, ACC>(L, a, tile, first, count, wave, lane, natom);
+    raster_points<K, CLS_PARTIAL, TILED, ACC, BAND>(L, a, tile, first, count, wave, lane, natom);
   else if constexpr (!TILED)
     raster_points<K, CLS_SLOW, false, ACC>(L, a, tile, first, count, wave, lane, natom);
+}
+
+// Flush of a tile rectangle (tw x th pixels at x0, y0): every covered tile
+// pixel once into the global buffer, leaving the entry PR_EMPTY for the next
+// batch.  Most covered pixels improve the global minimum, so the atomic is
+// issued without a prior read (no round trip on this path).
+__device__ __forceinline__ void flush_tile(uint64_t* tile, uint32_t tid, uint64_t* vb, uint32_t W, uint32_t x0,
+                                           uint32_t y0, uint32_t tw, uint32_t th, uint32_t& natom) {
+  const uint32_t n = tw * th;
+  for (uint32_t e = tid; e < n; e += THREADS) {
+    const uint64_t v = tile[e];
+    if (v != ~0ull) {
+      tile[e] = ~0ull;
+      const uint32_t ly = e / tw, lx = e - ly * tw;
+      __hip_atomic_fetch_min(vb + ((y0 + ly) * W + (x0 + lx)), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      natom++;
+    }
+  }
 }
 
 // One live batch of one view by the whole workgroup: its points into the LDS
 // tile (or straight into the global buffer), then the tile flush.  The LDS
 // tile is all PR_EMPTY between batches (the flush resets what it reads), so a
-// batch needs two barriers: one after its points, one after its flush.
-// publish: thread 0 stores next into s_next between the barriers (the
-// workgroup reads it after the second one).
+// batch needs two barriers: one after its points, one after its flush.  A
+// banded batch (rectangle up to a few tiles, at most one tile wide) streams its
+// points once per band of rows that fits the tile, with the same two barriers
+// per band.  publish: thread 0 stores next into s_next after the first
+// barrier (the workgroup reads it after the last one).
 __device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, uint32_t H, uint64_t* vb,
                                              const Streams& st, uint64_t* tile, uint32_t tid, uint32_t wave,
                                              uint32_t lane, bool publish, uint32_t next, uint32_t* s_next,
@@ -395,6 +419,21 @@ __device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, u
   L.tw8 = L.tw * 8u;
   const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
   const bool tiled = (mode >> 16) & 1u;
+  if ((mode >> 17) & 1u) {
+    const uint32_t th = L.th, bh = TILE_MAX / L.tw;  // rows per band (the rectangle is at most one tile wide)
+    L.cx = in_vgpr(uni(0x4B000000u + x0));
+    for (uint32_t by = 0; by < th; by += bh) {
+      L.th = min(bh, th - by);
+      L.cy = in_vgpr(uni(0x4B000000u + y0 + by));
+      // classify bands 10-bit batches only (more levels here would raise the kernel's register count)
+      raster_by_class<10, true, false, true>(cls, L, st, tile, first, count, wave, lane, natom);
+      __syncthreads();  // the band's points are all in the tile; s_next has been read
+      if (by == 0 && publish && tid == 0) *s_next = next;
+      flush_tile(tile, tid, L.vb, L.W, x0, y0 + by, L.tw, L.th, natom);
+      __syncthreads();  // tile clean again
+    }
+    return;
+  }
   L.cx = in_vgpr(uni(0x4B000000u + (tiled ? x0 : 0u)));
   L.cy = in_vgpr(uni(0x4B000000u + (tiled ? y0 : 0u)));
   if (tiled) {
@@ -408,23 +447,7 @@ __device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, u
   }
   __syncthreads();  // the batch's points are all in the tile; s_next has been read
   if (publish && tid == 0) *s_next = next;
-  if (tiled) {
-    // Flush: every covered tile pixel once into the global buffer, leaving
-    // the entry PR_EMPTY for the next batch.  Most covered pixels improve
-    // the global minimum, so the atomic is issued without a prior read
-    // (no round trip on this path).
-    const uint32_t n = L.tw * L.th;
-    for (uint32_t e = tid; e < n; e += THREADS) {
-      const uint64_t v = tile[e];
-      if (v != ~0ull) {
-        tile[e] = ~0ull;
-        const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
-        __hip_atomic_fetch_min(L.vb + ((y0 + ly) * L.W + (x0 + lx)), v, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        natom++;
-      }
-    }
-  }
+  if (tiled) flush_tile(tile, tid, L.vb, L.W, x0, y0, L.tw, L.th, natom);
   __syncthreads();  // tile clean again; s_next visible
 }
 

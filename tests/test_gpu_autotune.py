@@ -79,15 +79,15 @@ def test_every_tuning_renders_the_oracle_image(ctx, shapes, c1, terrain):
             [(terrain, c) for c in synth.stereo_cameras(synth.C2_SEED, 504, 560)]
     refs = [oracle.render(B, c.view, c.proj, c.width, c.height) for (_, B), c in cases]
     for i, s in enumerate(shapes):
-        for tile in sorted({0, s["tile_px"] // 2, 256}):
-            for wg in (0, 1):
-                say(f"autotune: shape {i} {s} tile_px={tile} wg_per_cu={wg}")
-                pr.pr_set_tuning(ctx.handle, shape=i, tile_px=tile, wg_per_cu=wg)
-                assert pr.pr_get_tuning(ctx.handle) == {"shape": i, "tile_px": tile, "wg_per_cu": wg}
-                for ((dc, _), c), (ref, st_ref) in zip(cases, refs):
-                    vb, fb, st = gpu_render(ctx, dc, c.view, c.proj, c.width, c.height)
-                    assert_vb_equal(vb, ref, c.width)
-                    oracle_stats_match(st, st_ref)
+        for tile, wg, bands in [(t, w, 0) for t in sorted({0, s["tile_px"] // 2, 256}) for w in (0, 1)] + \
+                               [(256, 0, 1), (256, 0, 64), (0, 0, 16)]:
+            say(f"autotune: shape {i} {s} tile_px={tile} wg_per_cu={wg} max_bands={bands}")
+            pr.pr_set_tuning(ctx.handle, shape=i, tile_px=tile, wg_per_cu=wg, max_bands=bands)
+            assert pr.pr_get_tuning(ctx.handle) == {"shape": i, "tile_px": tile, "wg_per_cu": wg, "max_bands": bands}
+            for ((dc, _), c), (ref, st_ref) in zip(cases, refs):
+                vb, fb, st = gpu_render(ctx, dc, c.view, c.proj, c.width, c.height)
+                assert_vb_equal(vb, ref, c.width)
+                oracle_stats_match(st, st_ref)
         pr.pr_set_tuning(ctx.handle, shape=i)
         cams = [c for (d, _), c in cases if d is terrain[0]]
         for vb, ((_, _), c), (ref, _) in zip(_views(ctx, terrain[0], cams), cases[2:], refs[2:]):
@@ -100,14 +100,14 @@ def test_tuning_argument_checks(ctx, shapes):
 
     n = len(shapes)
     bad = [dict(shape=n), dict(shape=0, tile_px=shapes[0]["tile_px"] + 1), dict(shape=0, wg_per_cu=1000),
-           dict(shape=0, reserved=1)]
+           dict(shape=0, max_bands=65)]
     pr.pr_set_tuning(ctx.handle, shape=n - 1, tile_px=128, wg_per_cu=1)
     for b in bad:
         with pytest.raises(pr.PrError, match="PR_EINVAL"):
             pr.pr_set_tuning(ctx.handle, **b)
-    assert pr.pr_get_tuning(ctx.handle) == {"shape": n - 1, "tile_px": 128, "wg_per_cu": 1}  # unchanged
+    assert pr.pr_get_tuning(ctx.handle) == {"shape": n - 1, "tile_px": 128, "wg_per_cu": 1, "max_bands": 0}
     assert pr.lib.pr_set_tuning(ctx.handle, None) == 0
-    assert pr.pr_get_tuning(ctx.handle) == {"shape": 0, "tile_px": 0, "wg_per_cu": 0}
+    assert pr.pr_get_tuning(ctx.handle) == {"shape": 0, "tile_px": 0, "wg_per_cu": 0, "max_bands": 0}
 
 
 def test_autotune_keeps_the_fastest_and_the_image(ctx, shapes, terrain):
@@ -126,7 +126,8 @@ def test_autotune_keeps_the_fastest_and_the_image(ctx, shapes, terrain):
     assert pr.pr_get_tuning(ctx.handle)["shape"] == 1  # an error leaves the tuning alone
     say("autotune: pr_autotune over 3 views")
     best, trials = pr.pr_autotune(ctx.handle, dc.handle, views, None, work, need, reps=2)
-    assert 2 * len(shapes) <= len(trials) <= 4 * len(shapes)
+    assert 2 * len(shapes) + 4 <= len(trials) <= 4 * len(shapes) + 4
+    assert {t["max_bands"] for t, _ in trials} == {0, 1, 2, 8, 16}
     assert {t["shape"] for t, _ in trials} == set(range(len(shapes)))
     assert all(ms > 0 for _, ms in trials)
     ms = [m for _, m in trials]
