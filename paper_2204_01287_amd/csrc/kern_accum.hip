@@ -21,6 +21,35 @@ namespace {
 // 4064 pixels: 16 KiB of thresholds + 64 KiB of sums (+ s_next), two workgroups in 160 KiB of LDS
 constexpr uint32_t HQS_TILE = 4064;
 
+// Thresholds fl32(closest depth * window) of a tw x th rectangle at (x0, y0)
+// into the LDS tile, and its sums zeroed.
+__device__ __forceinline__ void stage_band(const RenderArgs& a, float* thr, uint64_t* sums, uint32_t tid, uint32_t x0,
+                                           uint32_t y0, uint32_t tw, uint32_t th) {
+  const uint32_t n = tw * th;
+  for (uint32_t e = tid; e < n; e += THREADS) {
+    const uint32_t ly = e / tw, lx = e - ly * tw;
+    const uint64_t key = a.vb[(y0 + ly) * a.W + (x0 + lx)];
+    thr[e] = __uint_as_float((uint32_t)(key >> 32)) * a.window;
+    sums[2 * e] = 0;
+    sums[2 * e + 1] = 0;
+  }
+}
+
+// Every pixel of the rectangle with a point in its sums: two global additions.
+__device__ __forceinline__ void flush_band(const RenderArgs& a, const uint64_t* sums, uint32_t tid, uint32_t x0,
+                                           uint32_t y0, uint32_t tw, uint32_t th) {
+  const uint32_t n = tw * th;
+  for (uint32_t e = tid; e < n; e += THREADS) {
+    const uint64_t bn = sums[2 * e + 1];
+    if (bn >> 32) {
+      const uint32_t ly = e / tw, lx = e - ly * tw;
+      uint64_t* const g = a.accum + 2 * (uint64_t)((y0 + ly) * a.W + (x0 + lx));
+      __hip_atomic_fetch_add(g, sums[2 * e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(g + 1, bn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
   __shared__ float thr[HQS_TILE];
   __shared__ uint64_t sums[2 * HQS_TILE];
@@ -30,10 +59,10 @@ __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
   uint32_t* const qc = &a.hdr->queue[q][0];
   // batch order (Morton order for sorted clouds): the sums' lines of neighbouring
   // batches stay in the caches; measured faster than the render's order here
-  const uint32_t n = a.hdr->live_count + a.hdr->direct_count;
+  const uint32_t nlive = a.hdr->live_count + a.hdr->direct_count;
   if (tid == 0) {
     const uint32_t p = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
-    s_next = p < n ? a.order[p] : ~0u;
+    s_next = p < nlive ? a.order[p] : ~0u;
   }
   const Streams st = {a.low, a.med, a.high, a.colors};
   __syncthreads();
@@ -43,7 +72,7 @@ __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
     uint32_t grab = 0;
     if (tid == 0) {
       const uint32_t p = atomicAdd(qc, 1u) * RENDER_QUEUES + q;
-      grab = p < n ? a.order[p] : ~0u;
+      grab = p < nlive ? a.order[p] : ~0u;
     }
     const LiveBatch& rec = a.live[i];
     Loop L;
@@ -68,16 +97,30 @@ __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
     const int k = (int)(mode & 0xFFu), cls = (int)((mode >> 8) & 0xFFu);
     const uint32_t n = L.tw * L.th;
     const bool tiled = ((mode >> 16) & 1u) && n <= HQS_TILE;
+    // 10-bit batches with a proven rectangle too large for the tile but at most
+    // one tile wide: band by band (stage the band's thresholds, add, flush)
+    const bool banded = !tiled && k == 10 && ((mode >> 16) & 3u) && L.tw <= HQS_TILE;
+    if (banded) {
+      const uint32_t th = L.th, bh = HQS_TILE / L.tw;
+      L.cx = in_vgpr(uni(0x4B000000u + x0));
+      for (uint32_t by = 0; by < th; by += bh) {
+        L.th = min(bh, th - by);
+        L.cy = in_vgpr(uni(0x4B000000u + y0 + by));
+        stage_band(a, thr, sums, tid, x0, y0 + by, L.tw, L.th);
+        __syncthreads();
+        raster_by_class<10, true, true, true>(cls, L, st, sums, first, count, wave, lane, natom);
+        __syncthreads();  // the band's sums are complete; s_next has been read
+        if (by == 0 && tid == 0) s_next = grab;
+        flush_band(a, sums, tid, x0, y0 + by, L.tw, L.th);
+        __syncthreads();  // tile free again
+      }
+      i = uni(s_next);
+      continue;
+    }
     L.cx = in_vgpr(uni(0x4B000000u + (tiled ? x0 : 0u)));
     L.cy = in_vgpr(uni(0x4B000000u + (tiled ? y0 : 0u)));
     if (tiled) {
-      for (uint32_t e = tid; e < n; e += THREADS) {
-        const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
-        const uint64_t key = a.vb[(y0 + ly) * a.W + (x0 + lx)];
-        thr[e] = __uint_as_float((uint32_t)(key >> 32)) * a.window;
-        sums[2 * e] = 0;
-        sums[2 * e + 1] = 0;
-      }
+      stage_band(a, thr, sums, tid, x0, y0, L.tw, L.th);
       __syncthreads();
       if (k == 10) raster_by_class<10, true, true>(cls, L, st, sums, first, count, wave, lane, natom);
       else if (k == 20) raster_by_class<20, true, true>(cls, L, st, sums, first, count, wave, lane, natom);
@@ -89,17 +132,7 @@ __global__ void __launch_bounds__(THREADS) k_accum(RenderArgs a) {
     }
     __syncthreads();  // the batch's sums are complete; s_next has been read
     if (tid == 0) s_next = grab;
-    if (tiled) {
-      for (uint32_t e = tid; e < n; e += THREADS) {
-        const uint64_t bn = sums[2 * e + 1];
-        if (bn >> 32) {
-          const uint32_t ly = e / L.tw, lx = e - ly * L.tw;
-          uint64_t* const g = a.accum + 2 * (uint64_t)((y0 + ly) * a.W + (x0 + lx));
-          __hip_atomic_fetch_add(g, sums[2 * e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_add(g + 1, bn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-    }
+    if (tiled) flush_band(a, sums, tid, x0, y0, L.tw, L.th);
     __syncthreads();  // tile free for the next batch; s_next visible
     i = uni(s_next);
   }

@@ -129,7 +129,7 @@ __device__ __forceinline__ uint64_t sum_bn(uint32_t c) { return (uint64_t)((c >>
 // pixel's sums iff hw <= fl32(closest depth * window).  Tiled batches add into
 // the LDS sums (tile) behind the LDS threshold tile; others read the closest
 // depth from the visibility buffer and add into the global sums.
-template <int K, int CLS, bool TILED>
+template <int K, int CLS, bool TILED, bool BAND = false>
 __device__ __forceinline__ void four_points_acc(const Loop& L, uint64_t* tile, const Words& w, uint32_t nvalid) {
   const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
   const uint32_t Mw[4] = {w.m.x, w.m.y, w.m.z, w.m.w};
@@ -148,6 +148,7 @@ __device__ __forceinline__ void four_points_acc(const Loop& L, uint64_t* tile, c
     else
       pixel_fast(p, L.cx, L.cy, px, py);
     if constexpr (TILED) {
+      if constexpr (BAND) ok = ok && (py < L.th);  // rows of this band only
       const uint32_t e = __umul24(py, L.tw) + px;
       if (ok && p.hw <= L.thr[e]) {
         __hip_atomic_fetch_add(&tile[2 * e], sum_rg(Cw[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -176,7 +177,7 @@ template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
 __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const Words& w, uint32_t i0,
                                             uint32_t nvalid, uint32_t& natom) {
   if constexpr (ACC) {
-    four_points_acc<K, CLS, TILED>(L, tile, w, nvalid);
+    four_points_acc<K, CLS, TILED, BAND>(L, tile, w, nvalid);
     return;
   }
   const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};

@@ -133,3 +133,17 @@ def test_argument_checks(ctx, c1):
     with pytest.raises(pr.PrError, match="PR_EINVAL"):
         pr.pr_render_hqs(ctx.handle, dc.handle, cam.view, cam.proj, w, h, None, 1.01, vb, acc.data_ptr() + 8, 0, fb)
     pr.pr_sync(ctx.handle)
+
+
+def test_banded_batches(ctx, c1, terrain):
+    """A 256-pixel tile bound with a band limit of 64 makes most batches banded (several bands each) in both the
+    depth pass and the shading pass; sums and averages still equal the oracle."""
+    import paper_2204_01287_amd as pr
+
+    pr.pr_set_tuning(ctx.handle, tile_px=256, max_bands=64)
+    try:
+        for (dc, B), cam in [(c1, synth.c1_camera())] + [(terrain, c) for c in
+                                                          synth.stereo_cameras(synth.C2_SEED, 504, 560)]:
+            check(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, 1.01)
+    finally:
+        pr.pr_set_tuning(ctx.handle)
