@@ -366,6 +366,26 @@ def lod_leg(pr, ctx, n: int, steps: int, warmup: int):
                                    "speedup_vs_default": round(res["lod_px_100"]["ms_per_frame"] / t, 3)}
         pr.pr_set_tuning(ctx.handle)
         del work
+        # LOD with high-quality shading (window 1.01), the paper's VR combination, under the default tuning
+        accs = [torch.empty(2 * c.width * c.height, dtype=torch.int64, device="cuda") for c in cams]
+
+        def step_hqs():
+            for c, vb, acc, fb in zip(cams, vbs, accs, fbs):
+                pr.pr_render_hqs(ctx.handle, dc.handle, c.view, c.proj, c.width, c.height, o, 1.01, vb, acc,
+                                 0xFF000000, fb)
+
+        for _ in range(warmup):
+            step_hqs()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            step_hqs()
+            b.record(stream)
+        torch.cuda.synchronize()
+        res["lod_px_100_hqs"] = {"window": 1.01,
+                                 "ms_per_frame": round(float(np.mean([a.elapsed_time(b) for a, b in ev])), 4)}
+        del accs
         out[vname] = res
         log(f"lod {vname}: {res}")
     pr.pr_sync(ctx.handle)
