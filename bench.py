@@ -578,7 +578,9 @@ def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
     out = {"workload": "8 terrain clouds 1e7..1e9 (3.41e9 points), Poisson requests, 640x480/1920x1080/3840x2160",
            "requests": nreq, "rate_per_s": rate, "budget_bytes": budget, "resident_gb": round(resident / 1e9, 2),
            "load_s": round(t_load, 1), "mean_processed_points": round(total_pts / nreq)}
-    modes = {"batched": dict(nstreams=4, max_group=64), "one_view_per_launch": dict(nstreams=1, max_group=1)}
+    # the plain path queues every request on one stream as soon as it is admitted (no cap on groups in flight)
+    modes = {"batched": dict(nstreams=4, max_group=64),
+             "one_view_per_launch": dict(nstreams=1, max_group=1, depth=1 << 30)}
     for name, kw in modes.items():
         for load in ("offered", "saturated"):
             reqs = [Request(i, ci, cam, a if load == "offered" else 0.0) for i, (a, ci, cam) in enumerate(stream)]

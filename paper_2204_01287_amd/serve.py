@@ -15,6 +15,9 @@ A request names a resident cloud, a camera and an image size, and arrives at som
 
 Latency = completion (host clock when the group's event is seen complete) - arrival.  Every result equals the
 solo render of its request: the multi-view render equals the single-view render view by view.
+
+Scheduler holds the policy and no device state (launch, completion and the clock are callbacks), so that it can
+be exercised on the host alone; Server drives it with HIP streams, events and the library's launches.
 """
 from __future__ import annotations
 
@@ -48,6 +51,82 @@ class Done:
         return self.completed - self.arrival
 
 
+class Scheduler:
+    """Admission, grouping and stream assignment of the served mode, without device state.
+
+    run() calls launch(stream, cloud, group) -> token for each group it starts, is_done(token) -> bool to poll a
+    group, retire(token, group) when a polled group is complete, and now() for the clock (seconds since the run
+    started)."""
+
+    def __init__(self, nstreams: int = 4, budget_bytes: int = 4 << 30, max_group: int = B.PR_MAX_VIEWS,
+                 depth: int = 1, request_bytes=None):
+        if not 1 <= max_group <= B.PR_MAX_VIEWS:
+            raise ValueError("max_group must be in 1..PR_MAX_VIEWS")
+        if depth < 1 or nstreams < 1:
+            raise ValueError("depth and nstreams must be >= 1")
+        self.nstreams, self.budget, self.max_group, self.depth = nstreams, int(budget_bytes), max_group, depth
+        self.request_bytes = request_bytes or (lambda r: 12 * r.cam.width * r.cam.height)
+        self.peak_bytes = 0
+
+    def run(self, requests, launch, is_done, retire, now, idle=None):
+        """Serve every request (arrival times relative to the run); returns a list of Done in completion order."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending: deque = deque()  # arrived, not admitted
+        waiting = {}  # cloud -> deque of admitted requests not yet on the GPU
+        inflight = []  # [token, stream, group, bytes, launched]
+        load = [0] * self.nstreams
+        done = []
+        used = 0
+        nxt = 0
+        while len(done) < len(reqs):
+            t = now()
+            while nxt < len(reqs) and reqs[nxt].arrival <= t:
+                pending.append(reqs[nxt])
+                nxt += 1
+            retired = False
+            still = []
+            for g in inflight:
+                if is_done(g[0]):
+                    tdone = now()
+                    retire(g[0], g[2])
+                    for r in g[2]:
+                        done.append(Done(r.rid, r.cloud, r.arrival, g[4], tdone, len(g[2]), g[1]))
+                    used -= g[3]
+                    load[g[1]] -= 1
+                    retired = True
+                else:
+                    still.append(g)
+            inflight = still
+            admitted = []
+            while pending:
+                nbytes = self.request_bytes(pending[0])
+                if used + nbytes > self.budget and (inflight or admitted or waiting):
+                    break
+                used += nbytes
+                admitted.append(pending.popleft())
+            self.peak_bytes = max(self.peak_bytes, used)
+            for r in admitted:
+                waiting.setdefault(r.cloud, deque()).append(r)
+            launched_any = False
+            while waiting:
+                si = min(range(self.nstreams), key=lambda i: load[i])
+                if load[si] >= self.depth:
+                    break
+                cloud = min(waiting, key=lambda c: waiting[c][0].arrival)
+                q = waiting[cloud]
+                group = [q.popleft() for _ in range(min(self.max_group, len(q)))]
+                if not q:
+                    del waiting[cloud]
+                launched = now()
+                token = launch(si, cloud, group)
+                inflight.append([token, si, group, sum(self.request_bytes(r) for r in group), launched])
+                load[si] += 1
+                launched_any = True
+            if not admitted and not retired and not launched_any and idle is not None:
+                idle()
+        return done
+
+
 class Server:
     """Renders requests against resident, built clouds (DeviceCloud or handles) on one device."""
 
@@ -55,21 +134,18 @@ class Server:
                  max_group: int = B.PR_MAX_VIEWS, clear_rgba: int = 0xFF000000, on_result=None, depth: int = 1):
         import torch
 
-        if not 1 <= max_group <= B.PR_MAX_VIEWS:
-            raise ValueError("max_group must be in 1..PR_MAX_VIEWS")
-        if depth < 1:
-            raise ValueError("depth must be >= 1")
-        self.depth = depth  # groups in flight per stream
+        self.scheduler = Scheduler(nstreams, budget_bytes, max_group, depth, self.request_bytes)
         self.torch = torch
         self.device = device
         self.handles = [getattr(c, "handle", c) for c in clouds]
         self.streams = [torch.cuda.Stream(device) for _ in range(nstreams)]
         self.ctxs = [B.Context(device, stream=s) for s in self.streams]
-        self.budget = int(budget_bytes)
-        self.max_group = max_group
         self.clear_rgba = clear_rgba
         self.on_result = on_result  # callable(request, vb, fb): runs before the buffers are released
-        self.peak_bytes = 0
+
+    @property
+    def peak_bytes(self) -> int:
+        return self.scheduler.peak_bytes
 
     @staticmethod
     def request_bytes(r: Request) -> int:
@@ -95,63 +171,17 @@ class Server:
 
     def run(self, requests, idle_sleep: float = 0.0):
         """Serve every request (arrival times relative to the call); returns a list of Done in completion order."""
-        reqs = sorted(requests, key=lambda r: r.arrival)
-        pending: deque = deque()  # arrived, not admitted
-        waiting = {}  # cloud -> deque of admitted requests not yet on the GPU
-        inflight = []  # [event, stream, group, vbs, fbs, work, bytes, launched]
-        load = [0] * len(self.streams)
-        done = []
-        used = 0
-        nxt = 0
         t0 = time.perf_counter()
-        while len(done) < len(reqs):
-            now = time.perf_counter() - t0
-            while nxt < len(reqs) and reqs[nxt].arrival <= now:
-                pending.append(reqs[nxt])
-                nxt += 1
-            retired = False
-            still = []
-            for g in inflight:
-                if g[0].query():
-                    tdone = time.perf_counter() - t0
-                    for r, vb, fb in zip(g[2], g[3], g[4]):
-                        if self.on_result is not None:
-                            self.on_result(r, vb, fb)
-                        done.append(Done(r.rid, r.cloud, r.arrival, g[7], tdone, len(g[2]), g[1]))
-                    used -= g[6]
-                    load[g[1]] -= 1
-                    retired = True
-                else:
-                    still.append(g)
-            inflight = still
-            admitted = []
-            while pending:
-                nbytes = self.request_bytes(pending[0])
-                if used + nbytes > self.budget and (inflight or admitted or waiting):
-                    break
-                used += nbytes
-                admitted.append(pending.popleft())
-            self.peak_bytes = max(self.peak_bytes, used)
-            for r in admitted:
-                waiting.setdefault(r.cloud, deque()).append(r)
-            launched_any = False
-            while waiting:
-                si = min(range(len(self.streams)), key=lambda i: load[i])
-                if load[si] >= self.depth:
-                    break
-                cloud = min(waiting, key=lambda c: waiting[c][0].arrival)
-                q = waiting[cloud]
-                group = [q.popleft() for _ in range(min(self.max_group, len(q)))]
-                if not q:
-                    del waiting[cloud]
-                launched = time.perf_counter() - t0
-                ev, vbs, fbs, work = self._launch(si, cloud, group)
-                inflight.append([ev, si, group, vbs, fbs, work, sum(self.request_bytes(r) for r in group), launched])
-                load[si] += 1
-                launched_any = True
-            if not admitted and not retired and not launched_any:
-                if idle_sleep:
-                    time.sleep(idle_sleep)
+
+        def retire(token, group):
+            _, vbs, fbs, _ = token
+            if self.on_result is not None:
+                for r, vb, fb in zip(group, vbs, fbs):
+                    self.on_result(r, vb, fb)
+
+        done = self.scheduler.run(requests, launch=self._launch, is_done=lambda tok: tok[0].query(),
+                                  retire=retire, now=lambda: time.perf_counter() - t0,
+                                  idle=(lambda: time.sleep(idle_sleep)) if idle_sleep else None)
         for ctx in self.ctxs:
             B.pr_sync(ctx.handle)
         return done
