@@ -207,7 +207,8 @@ def test_terrain_stereo_pair(ctx, terrain_small):
 
 
 # ----------------------------------------------------------------- edges
-@pytest.mark.parametrize("n,S", [(0, 64), (1, 4), (5, 4), (10241, 10240), (20480, 10240), (1003, 64)])
+@pytest.mark.parametrize("n,S", [(0, 64), (1, 4), (5, 4), (10241, 10240), (20480, 10240), (1003, 64), (50003, 1000),
+                                 (600001, 262144)])
 def test_ragged_and_empty(ctx, n, S):
     xyz, rgba = synth.primitives(5, max(n, 1))
     xyz, rgba = xyz[:n], rgba[:n]
