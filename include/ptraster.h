@@ -32,8 +32,11 @@
  *     pixels hold PR_EMPTY.  Keys compare as unsigned 64-bit integers.
  *   - Limits: n < 2^32; 1 <= w, h <= 8192; batch sizes are multiples of 4.
  *   - Contexts and streams: a built cloud may be rendered and resolved through
- *     any context on its device (one context per HIP stream lets frames
- *     overlap); pr_build_batches uses the context that loaded it.
+ *     any context on its device; pr_build_batches uses the context that
+ *     loaded it.  With one context per HIP stream, pr_render_views frames
+ *     (each with a work buffer of its own) and resolves may overlap;
+ *     pr_render and pr_render_hqs keep their frame in the cloud's scratch
+ *     buffer, so those calls on one cloud must not overlap.
  */
 #ifndef PTRASTER_H
 #define PTRASTER_H
