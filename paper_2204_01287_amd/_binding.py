@@ -14,6 +14,14 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python {os.path.join(_HERE, 'build.py')}` "
         "(there is no fallback implementation)")
 
+# PyTorch ships its own HIP runtime (libamdhip64, soname libamdhip64.so.7, which
+# its libraries load by the unversioned file name).  Loaded first, it also
+# serves the library's libamdhip64.so.7 dependency, so the process has one HIP
+# runtime.  Loading the library first would bring in the system runtime and
+# leave torch to load a second one, and the second runtime to initialise finds
+# no device.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 PR_ADAPTIVE, PR_FORCE10, PR_FORCE20, PR_FORCE30 = 0, 10, 20, 30

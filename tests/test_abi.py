@@ -117,3 +117,17 @@ def test_every_listed_shape_is_compiled_in(pr):
                          check=True).stdout
     for w, d, t in shapes:
         assert f"ptr::raster_shape_w{w}_d{d}_t{t}()" in out, (w, d, t)
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Importing the binding (here through the served-mode module, as test collection does) maps one HIP runtime:
+    the one PyTorch ships, which then also serves the library.  A second runtime would find no device."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2204_01287_amd.serve\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n") % ROOT
+    r = subprocess.run(["python", "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    mapped = eval(r.stdout.strip().splitlines()[-1])
+    assert len(mapped) == 1, mapped
