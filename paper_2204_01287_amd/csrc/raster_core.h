@@ -298,10 +298,11 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
   if (nj > 0) {
     // PREFETCH register sets rotate through the wave's groups; each is
     // reloaded in place right after use, so every load is issued PREFETCH
-    // groups ahead of its use.  The body is branch-free: reloads are
-    // unconditional and clamped to the wave's last group, and a group
-    // index past the end repeats the last group with no valid points.
-    // Every wait then counts exactly the loads in flight.
+    // groups ahead of its use.  The rounds are branch-free: reloads are
+    // unconditional and clamped to the wave's last group, so every wait
+    // counts exactly the loads in flight.  Only whole rounds run this way;
+    // the last nj mod PREFETCH groups are then already loaded in the first
+    // register sets and are processed without reloads (no empty slots).
     const uint32_t glast = wave + (nj - 1) * WAVES;
     Words R[PREFETCH];
     uint32_t gi[PREFETCH];
@@ -314,16 +315,21 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
       // younger loads on every path
       __builtin_amdgcn_sched_barrier(0);
     }
-    for (uint32_t j = 0; j < nj; j += PREFETCH) {
+    const uint32_t whole = nj - nj % PREFETCH;
+    for (uint32_t j = 0; j < whole; j += PREFETCH) {
 #pragma unroll
       for (int d = 0; d < PREFETCH; ++d) {
-        const uint32_t g = gi[d];
-        four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + min(g, glast) * 256 + lane * 4,
-                                        g <= glast ? 4u : 0u, natom);
+        const uint32_t g = gi[d];  // <= glast in every whole round
+        four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + g * 256 + lane * 4, 4u, natom);
         gi[d] = g + PREFETCH * WAVES;
         R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
       }
     }
+    const uint32_t rest = nj - whole;  // groups gi[0 .. rest - 1], loaded in R[0 .. rest - 1]
+#pragma unroll
+    for (int d = 0; d < PREFETCH; ++d)
+      if ((uint32_t)d < rest)
+        four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + gi[d] * 256 + lane * 4, 4u, natom);
   }
   const uint32_t rem = count & 255u;
   if (rem && wave == 0) {  // ragged tail of the batch: scalar loads, per-point bounds
