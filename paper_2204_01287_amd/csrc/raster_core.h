@@ -289,7 +289,8 @@ __device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, ui
 
 // The points of one batch, split over the workgroup's waves: wave w takes the
 // groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
-// 16-byte load per word).  Wave 0 also takes the ragged tail.
+// 16-byte load per word).  The ragged tail goes to wave ngrp mod WAVES, the
+// next in that rotation (one of the waves with the fewest groups).
 template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
 __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
                               uint32_t wave, uint32_t lane, uint32_t& natom) {
@@ -332,7 +333,7 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
         four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + gi[d] * 256 + lane * 4, 4u, natom);
   }
   const uint32_t rem = count & 255u;
-  if (rem && wave == 0) {  // ragged tail of the batch: scalar loads, per-point bounds
+  if (rem && wave == ngrp % WAVES) {  // ragged tail of the batch: scalar loads, per-point bounds
     const uint32_t j0 = ngrp * 256 + lane * 4;
     const uint32_t nv = j0 < count ? min(4u, count - j0) : 0u;
     uint32_t l[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0}, h[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
