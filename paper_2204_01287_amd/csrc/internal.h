@@ -85,6 +85,7 @@ struct RenderArgs {
   uint32_t max_bands;    // classify: largest rectangle of a banded batch, in tiles
   const LodNode* nodes;  // LOD layouts: node per batch (else nullptr)
   float lod_px;          // > 0: cull nodes below the root whose cube projects below lod_px pixels
+  uint32_t clear_vb;     // classify: also fill vb (W x H) with PR_EMPTY
   // high-quality shading pass only
   const uint32_t* colors;
   uint64_t* accum;  // two words per pixel

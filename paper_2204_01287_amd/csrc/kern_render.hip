@@ -226,11 +226,21 @@ __device__ __forceinline__ bool decide_batch(const BatchRec& rec, const double (
 }
 
 // One batch per thread; live batches are appended to a compact list (wave
-// ballot + one atomic per wave).
+// ballot + one atomic per wave).  With clear_vb the launch also fills the
+// visibility buffer with PR_EMPTY (grid-stride 16-byte stores, overlapping the
+// prologue's arithmetic); the grid then has at least enough threads for that.
 template <bool CNT>
 __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
   const uint32_t b = blockIdx.x * 256u + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63;
+  if (a.clear_vb) {
+    const uint64_t npix = (uint64_t)a.W * a.H, n4 = npix / 2;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint4* const vb4 = reinterpret_cast<uint4*>(a.vb);
+    const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint64_t i = b; i < n4; i += stride) vb4[i] = ones;
+    if (b == 0 && (npix & 1)) a.vb[npix - 1] = ~0ull;
+  }
   const bool valid = b < a.nb;
   bool live = false;
   LiveBatch out;
@@ -422,8 +432,14 @@ hipError_t launch_clear(uint64_t* vb, uint64_t npix, DevBlock* dev, FrameHeader*
 }
 
 hipError_t launch_classify(const RenderArgs& a, hipStream_t s) {
-  if (a.nb == 0) return hipSuccess;
-  const uint32_t blocks = (a.nb + 255) / 256;
+  uint64_t blocks = ((uint64_t)a.nb + 255) / 256;
+  if (a.clear_vb) {
+    uint64_t cb = ((uint64_t)a.W * a.H / 2 + 255) / 256;
+    if (cb > 4096) cb = 4096;
+    if (cb < 1) cb = 1;
+    if (cb > blocks) blocks = cb;
+  }
+  if (blocks == 0) return hipSuccess;
   if (a.counters)
     hipLaunchKernelGGL(k_classify<true>, dim3(blocks), dim3(256), 0, s, a);
   else

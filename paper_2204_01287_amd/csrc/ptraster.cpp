@@ -413,16 +413,17 @@ pr_status check_render(const char* fn, pr_ctx* ctx, const pr_cloud* cloud, const
   return set_device(ctx);
 }
 
-// Clear (or, when accumulating, only reset the frame's work queue and
-// counters), classify and render one view; a receives the frame's arguments.
+// Reset the frame's work queues (and counters), classify (which also clears
+// the visibility buffer unless accumulating) and render one view; a receives
+// the frame's arguments.
 pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], const float proj[16], uint32_t w,
                        uint32_t h, const pr_render_opts& o, uint64_t* visbuf, ptr::RenderArgs& a) {
-  const uint64_t npix = (uint64_t)w * h;
   ptr::FrameHeader* hdr =
       reinterpret_cast<ptr::FrameHeader*>(static_cast<uint8_t*>(cloud->bufs.scratch) + ptr::small_scratch_bytes());
-  HIP_TRY(ptr::launch_clear(visbuf, o.accumulate ? 0 : npix, ctx->dev, hdr, o.counters ? 1 : 0, ctx->stream),
-          "clear");
+  // the frame header (and counters) here; the visibility buffer is filled by the classify launch
+  HIP_TRY(ptr::launch_clear(visbuf, 0, ctx->dev, hdr, o.counters ? 1 : 0, ctx->stream), "clear");
   std::memset(&a, 0, sizeof a);
+  a.clear_vb = o.accumulate ? 0u : 1u;
   a.low = static_cast<const uint32_t*>(cloud->bufs.low);
   a.med = static_cast<const uint32_t*>(cloud->bufs.med);
   a.high = static_cast<const uint32_t*>(cloud->bufs.high);

@@ -1,7 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration that bench.py times.
 
-Every GPU frame here is bench.py's: pr_clear, then pr_render with accumulate = 1, then pr_resolve with the
-clear colour 0xFF000000, on the context's stream, with the persistent render grid of pr_create.
+Every GPU frame here is bench.py's: pr_render with default options (its classify launch also clears the
+visibility buffer), then pr_resolve with the clear colour 0xFF000000, on the context's stream, with the persistent
+render grid of pr_create.
 
 C2 -- 100,000,000-point terrain (serpentine generation order, Morton build), orbit frames 0/15/30/45 at 1920x1080.
 The oracle builds and renders the same cloud.  The whole build (positions in render order, colours, permutation,
@@ -54,8 +55,8 @@ def _bench_frame(ctx, handle, cam):
     dev = torch.device("cuda", 0)
     vb = torch.empty(cam.width * cam.height, dtype=torch.int64, device=dev)
     fb = torch.empty(cam.width * cam.height, dtype=torch.int32, device=dev)
-    pr.pr_clear(ctx.handle, vb, cam.width, cam.height)
-    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height, pr.RenderOpts.make(accumulate=1), vb)
+    vb.fill_(7)  # stale contents: the frame must clear them
+    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height, None, vb)
     pr.pr_resolve(ctx.handle, handle, vb, cam.width, cam.height, CLEAR, fb)
     pr.pr_sync(ctx.handle)
     out_vb, out_fb = vb.cpu().numpy().view(np.uint64), fb.cpu().numpy().view(np.uint32)
