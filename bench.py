@@ -626,8 +626,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build renders on one GPU only (the multi-GPU sharding is a design, "
-              "not built); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the library renders on one GPU (sharding across GPUs is designed, not implemented); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

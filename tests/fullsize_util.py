@@ -15,7 +15,7 @@ from gpu_util import say
 S = 10240
 CLEAR = 0xFF000000
 CH = 64_000_000  # host chunk: 6250 whole batches
-WORKERS = 4      # build-check workers, each generator call on 4 threads: 16 host threads, the GPU host's share
+WORKERS = 4      # build-check workers, each generator call on 4 threads: 16 host threads
 RENDER_WORKERS = 16
 
 
