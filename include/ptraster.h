@@ -195,6 +195,23 @@ pr_status pr_views_work_bytes(const pr_cloud* cloud, uint32_t nviews, uint64_t* 
 pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
                           const pr_render_opts* opts, void* work, uint64_t work_bytes);
 
+/* For callers that cannot allocate device memory on the frame path (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): pr_render_views with its work area in a device array of
+ * PR_STATIC_WORK_BYTES that the library holds on each device it runs on
+ * (from pr_create on that device until the process ends), so the caller
+ * passes no work buffer.  Same frame, same results and the same errors as
+ * pr_render_views; this call allocates nothing.  Every call on one GPU shares
+ * that GPU's array: calls whose frames overlap on one GPU (several streams or
+ * threads) race and must be serialised by the caller (the frame resets
+ * what it reads of the array, so the contents a previous call left are
+ * harmless).  PR_ERANGE when the frame needs more than PR_STATIC_WORK_BYTES,
+ * i.e. when pr_views_work_bytes(cloud, nviews) exceeds it (for example
+ * 64 views of a 5e8-point cloud in 10,240-point batches). */
+#define PR_STATIC_WORK_BYTES (64ull << 20)
+pr_status pr_render_views_static(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                                 const pr_render_opts* opts);
+
 /* Load-time build of a level-of-detail layout (Sec. 3.5): the points are
  * already in render order (a layered point cloud: octree nodes level by
  * level) and grouped into nb variable-size batches given on the host as

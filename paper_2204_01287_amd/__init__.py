@@ -14,7 +14,7 @@ from ._binding import (  # noqa: F401
     PR_ADAPTIVE, PR_EMPTY, PR_FORCE10, PR_FORCE20, PR_FORCE30, PR_MAX_VIEWS, PrError, Sizes, CloudBufs, RenderOpts,
     Stats, View, pr_views_work_bytes, pr_render_views, pr_cloud_drop_load_buffers, pr_render_hqs, pr_cloud_sizes_spans,
     pr_build_batches_spans, LodNode, lod_nodes, BUFFER_FIELDS, RasterShape, Tuning, TuneTrial, pr_raster_shapes,
-    pr_set_tuning, pr_get_tuning, pr_autotune, pr_stream_probe,
+    pr_set_tuning, pr_get_tuning, pr_autotune, pr_stream_probe, pr_render_views_static, PR_STATIC_WORK_BYTES,
     LIB_PATH, lib, pr_last_error, pr_create, pr_destroy, pr_cloud_sizes, pr_load_points, pr_build_batches,
     pr_clear, pr_render, pr_resolve, pr_get_stats, pr_sync, pr_cloud_info, pr_cloud_free, EXPORTED,
     DeviceCloud, Context,

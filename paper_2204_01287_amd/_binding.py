@@ -34,7 +34,7 @@ EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_lo
             "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
             "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers", "pr_render_hqs",
             "pr_cloud_sizes_spans", "pr_build_batches_spans", "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning",
-            "pr_autotune", "pr_stream_probe"]
+            "pr_autotune", "pr_stream_probe", "pr_render_views_static"]
 
 
 class PrError(RuntimeError):
@@ -125,6 +125,7 @@ lib.pr_cloud_sizes_spans.argtypes = [_U64, _U64, ctypes.POINTER(Sizes)]
 lib.pr_build_batches_spans.argtypes = [_P, _P, _P, _P, _U64]
 lib.pr_render_hqs.argtypes = [_P, _P, _P, _P, _U32, _U32, ctypes.POINTER(RenderOpts), ctypes.c_float, _P, _P, _U32, _P]
 lib.pr_render_views.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64]
+lib.pr_render_views_static.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts)]
 lib.pr_sync.argtypes = [_P]
 lib.pr_raster_shapes.argtypes = [_P, ctypes.POINTER(RasterShape), _U32, ctypes.POINTER(_U32)]
 lib.pr_stream_probe.argtypes = [_P, _P, _P, _U64]
@@ -260,6 +261,16 @@ def pr_render_views(ctx, cloud, views, opts: RenderOpts | None, work, work_bytes
     _check(lib.pr_render_views(ctx, cloud, _views(views), len(views),
                                ctypes.byref(opts) if opts is not None else None, _ptr(work), work_bytes),
            "pr_render_views")
+
+
+def pr_render_views_static(ctx, cloud, views, opts: RenderOpts | None):
+    """views: sequence of (view, proj, w, h, visbuf); the work area is the library's static one."""
+    _check(lib.pr_render_views_static(ctx, cloud, _views(views), len(views),
+                                      ctypes.byref(opts) if opts is not None else None),
+           "pr_render_views_static")
+
+
+PR_STATIC_WORK_BYTES = 64 << 20
 
 
 def pr_stream_probe(ctx, src, dst, nbytes: int):

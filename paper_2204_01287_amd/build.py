@@ -13,7 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libptraster.so")
-SOURCES = ["ptraster.cpp", "kern_render.hip", "kern_accum.hip", "kern_build.hip", "kern_stream.hip"]
+SOURCES = ["ptraster.cpp", "kern_render.hip", "kern_accum.hip", "kern_build.hip", "kern_stream.hip",
+           "render_static.hip"]
 SHAPE_SOURCE = "kern_raster.hip"  # compiled once per workgroup shape
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

@@ -15,6 +15,12 @@
 
 #include "internal.h"
 
+namespace ptr {
+// render_static.hip: the library-held work area of pr_render_views_static
+hipError_t static_work_init(int device);
+void* static_work_addr(int device);
+}  // namespace ptr
+
 static_assert(sizeof(pr_lod_node) == sizeof(ptr::LodNode), "LOD node layout");
 static_assert(sizeof(pr_batch) == sizeof(ptr::BatchRec), "batch record layout");
 
@@ -189,6 +195,11 @@ pr_status pr_create(int device, void* hip_stream, pr_ctx** out) {
     for (int v = 0; v < 2; ++v) c->per_cu[i][v] = (uint32_t)shape_at(i).per_cu(v);
   c->accum_grid = ptr::accum_grid(device);
   c->tuning = {0, 0, 0, 0};
+  e = ptr::static_work_init(device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "static work area of pr_render_views_static (hipGetSymbolAddress)");
+  }
   e = hipMalloc(reinterpret_cast<void**>(&c->dev), 4096);
   if (e != hipSuccess) {
     delete c;
@@ -500,9 +511,12 @@ pr_status pr_views_work_bytes(const pr_cloud* cloud, uint32_t nviews, uint64_t* 
   return PR_OK;
 }
 
-pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
-                          const pr_render_opts* opts, void* work, uint64_t work_bytes) {
-  if (!ctx || !cloud || !views || !work) return fail(PR_EINVAL, "pr_render_views: NULL argument");
+namespace {
+
+// pr_render_views and pr_render_views_static: every step of the frame, with
+// the work area at work (work_bytes of device memory).
+pr_status render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                       const pr_render_opts* opts, void* work, uint64_t work_bytes) {
   if (cloud->ctx->device != ctx->device) return fail(PR_EINVAL, "pr_render_views: cloud lives on another device");
   if (!cloud->built) return fail(PR_ESTATE, "pr_render_views: cloud is not built (call pr_build_batches)");
   if (nviews < 1 || nviews > PR_MAX_VIEWS) return fail(PR_ERANGE, "pr_render_views: nviews %u not in 1..%d", nviews, PR_MAX_VIEWS);
@@ -593,6 +607,32 @@ pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* vie
   for (uint32_t v = 0; v < nviews; ++v) r.v[v] = {views[v].visbuf, views[v].w, views[v].h};
   HIP_TRY(shape_of(tune).render_views(r, nb * nchunks, o.counters ? 1 : 0, ctx->stream), "render views");
   return PR_OK;
+}
+
+}  // namespace
+
+pr_status pr_render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                          const pr_render_opts* opts, void* work, uint64_t work_bytes) {
+  if (!ctx || !cloud || !views || !work) return fail(PR_EINVAL, "pr_render_views: NULL argument");
+  return render_views(ctx, cloud, views, nviews, opts, work, work_bytes);
+}
+
+pr_status pr_render_views_static(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views, uint32_t nviews,
+                                 const pr_render_opts* opts) {
+  if (!ctx || !cloud || !views) return fail(PR_EINVAL, "pr_render_views_static: NULL argument");
+  if (!cloud->built) return fail(PR_ESTATE, "pr_render_views_static: cloud is not built (call pr_build_batches)");
+  if (nviews < 1 || nviews > PR_MAX_VIEWS)
+    return fail(PR_ERANGE, "pr_render_views_static: nviews %u not in 1..%d", nviews, PR_MAX_VIEWS);
+  const uint64_t need = ptr::views_work_bytes(cloud->nb, nviews);
+  if (need > (uint64_t)PR_STATIC_WORK_BYTES)
+    return fail(PR_ERANGE,
+                "pr_render_views_static: %llu batches x %u views need %llu bytes of work area; the library's "
+                "static area holds %llu (use pr_render_views with a work buffer)",
+                (unsigned long long)cloud->nb, nviews, (unsigned long long)need,
+                (unsigned long long)PR_STATIC_WORK_BYTES);
+  void* work = ptr::static_work_addr(ctx->device);
+  if (!work) return fail(PR_ESTATE, "pr_render_views_static: no static work area on device %d", ctx->device);
+  return render_views(ctx, cloud, views, nviews, opts, work, PR_STATIC_WORK_BYTES);
 }
 
 pr_status pr_clear(pr_ctx* ctx, uint64_t* visbuf, uint32_t w, uint32_t h) {
