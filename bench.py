@@ -135,10 +135,33 @@ def load_cloud(ctx, wl, chunk=64_000_000, on_chunk=None):
     return dict(handle=handle, mem=mem, bufs=bufs, n=n, nb=nb, t_gen=t_gen, t_build=t_build)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads for the host legs: the CPUs this process may run on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(wl, sample_n: int, seconds: float):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+    """The oracle, as it stands, on a bounded sample of the same workload: frames rendered concurrently on the
+    host's threads (one whole single-threaded oracle frame per thread at a time; frames are independent), and,
+    beside it, on one thread."""
+    import numpy as np
     import oracle
     import synth
+    from concurrent.futures import ThreadPoolExecutor
 
     t0 = time.perf_counter()
     if wl["name"].startswith("primitives"):
@@ -146,19 +169,46 @@ def cpu_baseline(wl, sample_n: int, seconds: float):
     else:
         xyz, rgba = synth.terrain(wl["seed"], sample_n, order=wl["order"])
     B = oracle.build_cloud(xyz, rgba, 10240, morton=wl["morton"])
+    del xyz, rgba
     t_build = time.perf_counter() - t0
-    pts, secs, frames = 0, 0.0, 0
-    while secs < seconds:
-        for cam in wl["cams"]:
+    nb = len(B.batches)
+    cams = wl["cams"]
+
+    def frame(i):
+        cam = cams[i % len(cams)]
+        vb, st = oracle.render(B, cam.view, cam.proj, cam.width, cam.height)
+        return st["points"], int(np.count_nonzero(vb != oracle.EMPTY))
+
+    # one thread first (at least one frame per camera, about a third of the time budget)
+    pts1, secs1, frames1, cover = 0, 0.0, 0, []
+    while secs1 < seconds / 3 or frames1 < len(cams):
+        t = time.perf_counter()
+        p, c = frame(frames1)
+        secs1 += time.perf_counter() - t
+        pts1 += p
+        cover.append(c)
+        frames1 += 1
+    threads = host_threads()
+    per_round = 2 * threads
+    pts, frames, secs = 0, 0, 0.0
+    with ThreadPoolExecutor(threads) as ex:
+        while secs < seconds:
             t = time.perf_counter()
-            _, st = oracle.render(B, cam.view, cam.proj, cam.width, cam.height)
+            res = list(ex.map(frame, range(frames, frames + per_round)))
             secs += time.perf_counter() - t
-            pts += st["points"]
-            frames += 1
-    return dict(value=round(pts / secs / 1e9, 6), unit="Gpoints/s", cores=1, kind="oracle",
-                sample=f"{wl['name'].split('_')[0]} generator at {sample_n} points (Morton={wl['morton']}), "
-                       f"same cameras and resolution, {frames} oracle renders, {pts} processed points in "
-                       f"{secs:.1f} s; oracle build {t_build:.1f} s not included; single thread")
+            for k, (p, c) in enumerate(res):
+                pts += p
+                assert c == cover[(frames + k) % len(cams)], "oracle frames differ between runs"
+            frames += per_round
+    label = wl["name"].split("_")[0]
+    return dict(value=round(pts / secs / 1e9, 6), unit="Gpoints/s", cores=threads, kind="oracle",
+                cpu_model=cpu_model(),
+                sample=f"{label} generator at {sample_n} points (Morton={wl['morton']}, {nb} batches of 10240), "
+                       f"same cameras and resolution; {frames} whole oracle frames rendered concurrently on "
+                       f"{threads} threads, {pts} processed points in {secs:.1f} s; oracle build {t_build:.1f} s "
+                       f"not included",
+                single_thread={"value": round(pts1 / secs1 / 1e9, 6), "unit": "Gpoints/s", "frames": frames1,
+                               "seconds": round(secs1, 2)})
 
 
 def profile_counters(kernel_src_hash: str, workload_name: str) -> dict:
@@ -201,6 +251,38 @@ def measure_stream(pr, ctx, nbytes: int = 4 << 30, reps: int = 10) -> dict:
     return out
 
 
+def roofline(alg_bytes: float, ms: float, what: str, bytes_note: str) -> dict:
+    """HBM roofline of a timed call: algorithmic bytes over its event-timed span, against 8 TB/s."""
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": what, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(alg_bytes), "bytes": bytes_note,
+            "span_ms": round(ms, 4)}
+
+
+def render_bytes(st: dict) -> int:
+    """Algorithmic bytes of the point loop of a frame: its coordinate words plus one 80-byte render record per live
+    (batch, view)."""
+    return st["words_bytes"] + 80 * sum(st["level_batches"])
+
+
+def timed_ms(fn, steps: int, warmup: int) -> float:
+    """Mean span of fn() over steps calls, HIP events on the current stream, after warmup untimed calls."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
 def kernel_hash():
     import hashlib
 
@@ -239,7 +321,13 @@ def multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, plain
         return [a.elapsed_time(b) for a, b in ev]
 
     mv = timed(frame_views)
+    pr.pr_render_views(ctx.handle, cloud["handle"], vlist, pr.RenderOpts.make(counters=1), work, need)
+    st = pr.pr_get_stats(ctx.handle)
+    rv_ms = timed_ms(lambda: pr.pr_render_views(ctx.handle, cloud["handle"], vlist, None, work, need), steps, warmup)
     res = {"launches": "one clear, one classify, one render launch for both eyes; resolve per eye",
+           "roofline": roofline(render_bytes(st), rv_ms, "pr_render_views (clear, classify, render of both eyes)",
+                                "coordinate words streamed once per batch at the highest level among its live "
+                                "views + 80 B per live (batch, view) record"),
            "ms_per_step": round(float(np.mean(mv)), 4),
            "gpts": round(processed / (float(np.mean(mv)) * 1e-3) / 1e9, 3),
            "frame_ms_p50": round(float(np.percentile(mv, 50)), 4),
@@ -287,8 +375,22 @@ def hqs_leg(pr, ctx, cloud, cams, processed, steps, warmup, window=1.01):
     torch.cuda.synchronize()
     pr.pr_sync(ctx.handle)
     t = [a.elapsed_time(b) for a, b in ev]
+    alg = 0
+    for c, (vb, acc, fb) in zip(cams, bufs):
+        pr.pr_render(ctx.handle, cloud["handle"], c.view, c.proj, c.width, c.height, pr.RenderOpts.make(counters=1),
+                     vb)
+        st = pr.pr_get_stats(ctx.handle)
+        px = c.width * c.height
+        # classify (32 B per batch, clear 8 B/px), render, zeroed sums (16 B/px), shading pass (words again,
+        # 4 B colour per processed point, records, 8 B/px closest depths), averaging resolve (16 B/px + 4 B/px)
+        alg += 32 * st["batches"] + 8 * px + render_bytes(st) + 16 * px + render_bytes(st) + 4 * st["points"] + \
+            8 * px + 20 * px
     res = {"window": window, "ms_per_step": round(float(np.mean(t)), 4),
-           "gpts": round(processed / (float(np.mean(t)) * 1e-3) / 1e9, 3)}
+           "gpts": round(processed / (float(np.mean(t)) * 1e-3) / 1e9, 3),
+           "roofline": roofline(alg, float(np.mean(t)), "pr_render_hqs of both eyes (render, shading pass, resolve)",
+                                "classify 32 B/batch + clear 8 B/px, render words + 80 B/record, sums zeroed "
+                                "16 B/px, shading words + 4 B colour per processed point + 80 B/record + 8 B/px "
+                                "closest depths, resolve 20 B/px")}
     log(f"high-quality shading: {res}")
     return res
 
@@ -318,11 +420,14 @@ def lod_leg(pr, ctx, n: int, steps: int, warmup: int):
         fbs = [torch.empty(c.width * c.height, dtype=torch.int32, device="cuda") for c in cams]
         res = {}
         for lod_px in (0.0, 100.0):
-            processed = 0
+            processed, alg = 0, 0
             for c, vb in zip(cams, vbs):
                 pr.pr_render(ctx.handle, dc.handle, c.view, c.proj, c.width, c.height,
                              pr.RenderOpts.make(counters=1, lod_px=lod_px), vb)
-                processed += pr.pr_get_stats(ctx.handle)["points"]
+                st = pr.pr_get_stats(ctx.handle)
+                processed += st["points"]
+                # classify 32 B/batch + clear 8 B/px, render, resolve 12 B/px
+                alg += 32 * st["batches"] + 8 * c.width * c.height + render_bytes(st) + 12 * c.width * c.height
             o = pr.RenderOpts.make(lod_px=lod_px)
 
             def step():
@@ -342,7 +447,10 @@ def lod_leg(pr, ctx, n: int, steps: int, warmup: int):
             t = float(np.mean([a.elapsed_time(b) for a, b in ev]))
             res[f"lod_px_{int(lod_px)}"] = {"ms_per_frame": round(t, 4), "processed_points": processed,
                                             "gpts": round(processed / (t * 1e-3) / 1e9, 3),
-                                            "all_points_rate_gpts": round(n * len(cams) / (t * 1e-3) / 1e9, 3)}
+                                            "all_points_rate_gpts": round(n * len(cams) / (t * 1e-3) / 1e9, 3),
+                                            "roofline": roofline(alg, t, "pr_render + pr_resolve per view",
+                                                                 "classify 32 B/batch + clear 8 B/px, render "
+                                                                 "words + 80 B/record, resolve 12 B/px")}
         res["frame_speedup"] = round(res["lod_px_0"]["ms_per_frame"] / res["lod_px_100"]["ms_per_frame"], 3)
         # the autotuner on the LOD frame (lod_px 100): winner, then the same plain frame under it
         need = pr.pr_views_work_bytes(dc.handle, len(cams))
@@ -509,7 +617,15 @@ def camera_array_leg(pr, ctx, n: int, steps: int, warmup: int, sizes=(5120, 1024
                 pr.pr_resolve(ctx.handle, c.handle, vb, cam.width, cam.height, 0xFF000000, fb)
 
         p_ms, m_ms = timed(plain), timed(multi)
+        pr.pr_render_views(ctx.handle, c.handle, vlist, pr.RenderOpts.make(counters=1), work, need)
+        st = pr.pr_get_stats(ctx.handle)
+        npx = sum(cam.width * cam.height for cam in cams)
+        chunks = (len(cams) + 15) // 16
+        alg = 32 * c.nb * chunks + 8 * npx + render_bytes(st) + 12 * npx
         out[name] = {"batch_size": S, "tuning": t, "processed_points": processed,
+                     "roofline_multiview": roofline(alg, m_ms, "pr_render_views of 64 views + 64 resolves",
+                                                    "classify 32 B/batch per 16 views + clear 8 B/px, words once "
+                                                    "per batch and classify launch + 80 B/record, resolve 12 B/px"),
                      "plain_64_launches_ms": round(p_ms, 3), "multiview_one_launch_ms": round(m_ms, 3),
                      "plain_gpts": round(processed / (p_ms * 1e-3) / 1e9, 2),
                      "multiview_gpts": round(processed / (m_ms * 1e-3) / 1e9, 2),
@@ -541,11 +657,88 @@ class _Keep:
         pass
 
 
-def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
-    """Served workload: 8 resident terrain clouds (3.41e9 points), a seeded Poisson request stream with random
-    cameras and image sizes 640x480 / 1920x1080 / 3840x2160, admission by visibility + framebuffer bytes.
-    Continuous batching (grouped multi-view launches on 4 streams) against one view per launch on one stream:
-    latency at the offered rate, and capacity with every request arriving at once."""
+def c2_leg(pr, ctx, steps: int, warmup: int, n: int = 100_000_000):
+    """The paper's bandwidth and ordering comparisons on the 1e8-point terrain, over the 60-frame orbit at
+    1920x1080 (per frame: pr_render + pr_resolve): adaptive precision (4/8/12-byte loads, Sec. 3.3) against fixed
+    12-byte loads (PR_FORCE30), Morton order against the generation order (10 m tiles in serpentine strips,
+    Sec. 4.2), and the default prefetch depth against one group in flight per wave (Sec. 3.4).  Every variant
+    renders the same points; only what each frame loads, in which order, and how far ahead, differs."""
+    import numpy as np
+    import torch
+    import synth
+
+    cams = [synth.orbit_camera(f) for f in range(60)]
+    stream = torch.cuda.current_stream()
+    shapes = pr.pr_raster_shapes(ctx.handle)
+    d1 = next(i for i, sh in enumerate(shapes) if sh["depth"] == 1 and sh["waves"] == shapes[0]["waves"] and
+              sh["tile_px"] == shapes[0]["tile_px"])
+    clouds = {}
+    t0 = time.perf_counter()
+    for order, morton in (("morton", True), ("generation", False)):
+        clouds[order] = load_cloud(ctx, dict(name=f"terrain_1e8_{order}", seed=synth.C2_SEED, n=n, morton=morton,
+                                             order=1))
+    log(f"c2: two 1e8-point builds in {time.perf_counter() - t0:.1f} s")
+    w, h = cams[0].width, cams[0].height
+    vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
+    fb = torch.empty(w * h, dtype=torch.int32, device="cuda")
+    variants = {"morton_adaptive": ("morton", pr.PR_ADAPTIVE, 0),
+                "morton_force30": ("morton", pr.PR_FORCE30, 0),
+                "generation_adaptive": ("generation", pr.PR_ADAPTIVE, 0),
+                "morton_adaptive_prefetch1": ("morton", pr.PR_ADAPTIVE, d1)}
+    out = {"points": n, "frames": 60, "view": f"{w}x{h}", "prefetch1_shape": shapes[d1]}
+    for name, (order, prec, shape) in variants.items():
+        c = clouds[order]
+        pr.pr_set_tuning(ctx.handle, shape=shape)
+        processed, alg = 0, 0
+        for cam in cams:  # counters pass: processed points and loaded words of every frame
+            pr.pr_render(ctx.handle, c["handle"], cam.view, cam.proj, w, h,
+                         pr.RenderOpts.make(precision=prec, counters=1), vb)
+            st = pr.pr_get_stats(ctx.handle)
+            processed += st["points"]
+            lp = st["level_points"]
+            alg += 4 * lp[0] + 8 * lp[1] + 12 * lp[2] + 80 * (st["batches"] - st["culled"])
+        o = pr.RenderOpts.make(precision=prec)
+
+        def orbit():
+            for cam in cams:
+                pr.pr_render(ctx.handle, c["handle"], cam.view, cam.proj, w, h, o, vb)
+                pr.pr_resolve(ctx.handle, c["handle"], vb, w, h, 0xFF000000, fb)
+
+        for _ in range(max(1, warmup)):
+            orbit()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            orbit()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) / len(cams)
+        out[name] = {"ms_per_frame": round(ms, 4), "processed_points_per_frame": processed // len(cams),
+                     "gpts": round(processed / len(cams) / (ms * 1e-3) / 1e9, 2),
+                     "algorithmic_gb_per_frame": round(alg / len(cams) / 1e9, 4),
+                     "algorithmic_gbs": round(alg / len(cams) / (ms * 1e-3) / 1e9, 1)}
+        log(f"c2 {name}: {out[name]}")
+    pr.pr_set_tuning(ctx.handle)
+    base = out["morton_adaptive"]["ms_per_frame"]
+    out["speedup_adaptive_vs_force30"] = round(out["morton_force30"]["ms_per_frame"] / base, 3)
+    out["speedup_morton_vs_generation"] = round(out["generation_adaptive"]["ms_per_frame"] / base, 3)
+    out["speedup_prefetch_vs_depth1"] = round(out["morton_adaptive_prefetch1"]["ms_per_frame"] / base, 3)
+    pr.pr_sync(ctx.handle)
+    for c in clouds.values():
+        pr.pr_cloud_free(c["handle"])
+        c["mem"].clear()
+    torch.cuda.empty_cache()
+    return out
+
+
+def served_leg(pr, ctx, nreq: int, rates, budget: int):
+    """Served workload: 8 resident terrain clouds (3.41e9 points), seeded Poisson request streams with random
+    cameras and image sizes 640x480 / 1920x1080 / 3840x2160, admission by device bytes (visibility + frame buffers
+    and the work-area share).  Continuous batching (grouped multi-view launches on 4 streams) against one view per
+    launch on the same 4 streams (only the grouping differs), and against one view per launch with every request
+    queued on one stream as soon as it is admitted: latency at each offered rate, and capacity with every request
+    arriving at once."""
     import numpy as np
     import torch
     import synth
@@ -556,6 +749,7 @@ def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
     for seed, n in synth.SERVED_CLOUDS:
         c = load_cloud(ctx, dict(name=f"served_{seed}", seed=seed, n=n, morton=True, order=0))
         pr.pr_cloud_drop_load_buffers(c["handle"])
+        pr.pr_sync(ctx.handle)
         for f in ("xyz", "rgba", "perm", "scratch"):
             c["mem"][f] = None
         torch.cuda.empty_cache()
@@ -563,38 +757,54 @@ def served_leg(pr, ctx, nreq: int, rate: float, budget: int):
     t_load = time.perf_counter() - t0
     resident = sum(t.numel() for c in clouds for t in c["mem"].values() if t is not None)
     log(f"served: {len(clouds)} clouds resident ({resident / 1e9:.1f} GB) after {t_load:.1f} s")
-    stream = synth.request_stream(5, nreq, rate, [s for s, _ in synth.SERVED_CLOUDS])
+    seeds = [s for s, _ in synth.SERVED_CLOUDS]
+    streams = {r: synth.request_stream(5, nreq, r, seeds) for r in rates}
     handles = [c["handle"] for c in clouds]
-    # processed points of every request (Table 2 definition), counted solo once
+    # processed points of every request (Table 2 definition), counted solo once (the same requests at every rate)
+    first = streams[rates[0]]
+    for r in rates[1:]:
+        assert [(ci, cam.width) for _, ci, cam in streams[r]] == [(ci, cam.width) for _, ci, cam in first]
     pts = []
-    need = pr.pr_views_work_bytes(handles[-1], 1)
+    need = max(pr.pr_views_work_bytes(h, 1) for h in handles)
     work = torch.empty(need, dtype=torch.uint8, device="cuda")
-    for a, ci, cam in stream:
-        vb = torch.empty(cam.width * cam.height, dtype=torch.int64, device="cuda")
+    vbmax = torch.empty(max(cam.width * cam.height for _, _, cam in first), dtype=torch.int64, device="cuda")
+    for a, ci, cam in first:
+        vb = vbmax[: cam.width * cam.height]
         pr.pr_render_views(ctx.handle, handles[ci], [(cam.view, cam.proj, cam.width, cam.height, vb)],
                            pr.RenderOpts.make(counters=1), work, need)
         pts.append(pr.pr_get_stats(ctx.handle)["points"])
+    del work, vbmax
     total_pts = float(sum(pts))
     out = {"workload": "8 terrain clouds 1e7..1e9 (3.41e9 points), Poisson requests, 640x480/1920x1080/3840x2160",
-           "requests": nreq, "rate_per_s": rate, "budget_bytes": budget, "resident_gb": round(resident / 1e9, 2),
-           "load_s": round(t_load, 1), "mean_processed_points": round(total_pts / nreq)}
-    # the plain path queues every request on one stream as soon as it is admitted (no cap on groups in flight)
+           "requests": nreq, "rates_per_s": list(rates), "budget_bytes": budget,
+           "resident_gb": round(resident / 1e9, 2), "load_s": round(t_load, 1),
+           "mean_processed_points": round(total_pts / nreq)}
     modes = {"batched": dict(nstreams=4, max_group=64),
-             "one_view_per_launch": dict(nstreams=1, max_group=1, depth=1 << 30)}
+             "one_view_per_launch": dict(nstreams=4, max_group=1),
+             "one_view_per_launch_1stream_queued": dict(nstreams=1, max_group=1, depth=1 << 30)}
+    loads = [(f"offered_{int(r)}", r) for r in rates] + [("saturated", None)]
     for name, kw in modes.items():
-        for load in ("offered", "saturated"):
-            reqs = [Request(i, ci, cam, a if load == "offered" else 0.0) for i, (a, ci, cam) in enumerate(stream)]
+        for load, rate in loads:
+            if name.endswith("queued") and rate is not None:
+                continue  # capacity only
+            src = streams[rate if rate is not None else rates[0]]
+            reqs = [Request(i, ci, cam, a if rate is not None else 0.0) for i, (a, ci, cam) in enumerate(src)]
             srv = Server(handles, budget_bytes=budget, **kw)
             done = srv.run(reqs)
+            peak = srv.peak_bytes
             srv.close()
             lat = np.array([d.latency for d in done]) * 1e3
             span = max(d.completed for d in done) - min(r.arrival for r in reqs)
             out[f"{name}_{load}"] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
                                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
                                      "gpts": round(total_pts / span / 1e9, 2), "span_s": round(span, 3),
-                                     "mean_group": round(float(np.mean([d.group for d in done])), 2)}
+                                     "mean_group": round(float(np.mean([d.group for d in done])), 2),
+                                     "peak_admitted_bytes": int(peak)}
             log(f"served {name} {load}: {out[f'{name}_{load}']}")
-    out["capacity_speedup"] = round(out["batched_saturated"]["gpts"] / out["one_view_per_launch_saturated"]["gpts"], 3)
+    out["capacity_speedup_same_streams"] = round(out["batched_saturated"]["gpts"] /
+                                                 out["one_view_per_launch_saturated"]["gpts"], 3)
+    out["capacity_speedup_vs_1stream_queued"] = round(out["batched_saturated"]["gpts"] /
+                                                      out["one_view_per_launch_1stream_queued_saturated"]["gpts"], 3)
     for c in clouds:
         pr.pr_cloud_free(c["handle"])
         c["mem"].clear()
@@ -613,12 +823,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true", help="skip the served-mode leg")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 1e8-point precision / order / prefetch leg")
     ap.add_argument("--lod-points", type=int, default=500_000_000, help="points of the LOD leg (0: skip)")
     ap.add_argument("--array-points", type=int, default=500_000_000,
                     help="points of the 64-camera array leg with the batch-size autotuner (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner leg on the headline workload")
-    ap.add_argument("--served-requests", type=int, default=1000)
-    ap.add_argument("--served-rate", type=float, default=500.0)
+    ap.add_argument("--served-requests", type=int, default=10000)
+    ap.add_argument("--served-rates", type=str, default="500,4000",
+                    help="offered request rates per second (comma-separated)")
     ap.add_argument("--served-budget", type=int, default=4 << 30, help="bytes of visibility + frame buffers in flight")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write kernel (HBM counter calibration)")
@@ -664,8 +876,7 @@ def main():
                      pr.RenderOpts.make(counters=1), vb)
         per_view.append(pr.pr_get_stats(ctx.handle))
     processed = sum(s["points"] for s in per_view)
-    alg_bytes = [4 * s["level_points"][0] + 8 * s["level_points"][1] + 12 * s["level_points"][2] + 32 * s["batches"]
-                 for s in per_view]
+    alg_bytes = [render_bytes(s) for s in per_view]  # k_render: words of live batches + 80 B per live record
     log(f"per-view counters: {per_view}")
 
     stream = torch.cuda.current_stream()
@@ -761,12 +972,15 @@ def main():
     pr.pr_cloud_free(cloud["handle"])
     cloud["mem"].clear()
     torch.cuda.empty_cache()
+    if not args.no_c2:
+        out["c2"] = c2_leg(pr, ctx, min(args.steps, 10), args.warmup)
     if args.lod_points:
         out["lod"] = lod_leg(pr, ctx, args.lod_points, args.steps, args.warmup)
     if args.array_points:
         out["camera_array"] = camera_array_leg(pr, ctx, args.array_points, min(args.steps, 10), min(args.warmup, 2))
     if not args.no_served:
-        out["served"] = served_leg(pr, ctx, args.served_requests, args.served_rate, args.served_budget)
+        out["served"] = served_leg(pr, ctx, args.served_requests,
+                                   [float(r) for r in args.served_rates.split(",")], args.served_budget)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl["n"]), args.cpu_seconds)

@@ -123,11 +123,16 @@ typedef struct {
 /* Frame counters (Table 2 definitions): processed batches = every batch,
  * processed points = points in batches that were not culled; atomics = number
  * of 64-bit atomic minimum calls issued, which depends on timing and is
- * reported, never compared. */
+ * reported, never compared.  words_bytes = bytes of coordinate words the
+ * frame must stream (4, 8 or 12 per point of a live batch at 10, 20 or 30
+ * bits; in a pr_render_views frame once per batch and classify launch, at the
+ * highest level among the batch's live views there), the algorithmic HBM
+ * bytes of the point loop. */
 typedef struct {
   uint64_t batches, culled, points;
   uint64_t level_batches[3], level_points[3]; /* index 0, 1, 2 = 10, 20, 30 bits */
   uint64_t atomics;
+  uint64_t words_bytes;
 } pr_stats;
 
 /* Message of the last failed call on this thread (never NULL). */
@@ -245,7 +250,8 @@ pr_status pr_render(pr_ctx* ctx, const pr_cloud* cloud, const float view[16], co
  * exactly as pr_render (the closest depth per pixel), then every drawn point
  * whose w is within the depth window of its pixel's closest point,
  *   hw <= fl32(w_closest * window)   (binary32 product; window >= 1, e.g.
- *                                     1.01 = "1 % behind the closest point"),
+ *                                     1.01 lets points up to one percent farther
+ *                                     than the pixel's closest point join),
  * adds its colour and a count to accum (uint64[2*h*w], device, 16-byte
  * aligned, zeroed by this call): accum[2p] += R + G * 2^32, accum[2p+1] +=
  * B + 2^32, with R, G, B the low three bytes of the colour (additions wrap

@@ -500,7 +500,8 @@ void or_resolve(const uint64_t* vb, uint64_t npix, const uint32_t* colors, uint6
  *   - the closest depth of pixel p is the depth of its visibility-buffer key,
  *     hw_min = bits (vb[p] >> 32) as binary32 (vb from or_render, same opts);
  *   - point i (drawn by O7 at pixel p) joins iff hw_i <= fl32(hw_min * window),
- *     one binary32 multiplication (window >= 1; 1.01 = "1 % behind");
+ *     one binary32 multiplication (window >= 1; 1.01 admits points up to one percent
+ *     farther than the closest one);
  *   - the sums are the paper's two 64-bit words per pixel holding four 32-bit
  *     fields: acc[2p] += R + G * 2^32, acc[2p + 1] += B + 2^32 (count), with
  *     R, G, B the low three bytes of the point's colour; additions wrap

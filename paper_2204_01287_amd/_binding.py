@@ -98,12 +98,12 @@ class TuneTrial(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("culled", ctypes.c_uint64), ("points", ctypes.c_uint64),
                 ("level_batches", ctypes.c_uint64 * 3), ("level_points", ctypes.c_uint64 * 3),
-                ("atomics", ctypes.c_uint64)]
+                ("atomics", ctypes.c_uint64), ("words_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         return {"batches": self.batches, "culled": self.culled, "points": self.points,
                 "level_batches": list(self.level_batches), "level_points": list(self.level_points),
-                "atomics": self.atomics}
+                "atomics": self.atomics, "words_bytes": self.words_bytes}
 
 
 _P, _U64, _U32, _I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
@@ -402,8 +402,11 @@ class DeviceCloud:
         self.nb = pr_cloud_info(self.handle)[1]
 
     def drop_load_buffers(self):
-        """Keep only what rendering reads; frees positions, input colours, permutation and scratch."""
+        """Keep only what rendering reads; frees positions, input colours, permutation and scratch.  Waits for
+        the context's stream first: a pr_render enqueued there may still use the scratch buffer, and the caching
+        allocator may hand the freed memory to work on another stream at once."""
         pr_cloud_drop_load_buffers(self.handle)
+        pr_sync(self.ctx.handle)
         for f in ("xyz", "rgba", "perm", "scratch"):
             self.mem[f] = None
 

@@ -22,11 +22,11 @@ static_assert(sizeof(LodNode) == 48, "LOD node record is 48 bytes");
 
 // Device-side context block (one per pr_ctx), 4 KiB.
 struct DevBlock {
-  uint64_t stats[16];     // batches, culled, points, lvl_b[3], lvl_p[3], atomics
+  uint64_t stats[16];     // batches, culled, points, lvl_b[3], lvl_p[3], atomics, words bytes
   uint32_t flags[16];     // [0] non-finite coordinate seen
   uint64_t sink;          // streaming read probe
 };
-enum { ST_BATCHES = 0, ST_CULLED, ST_POINTS, ST_LB0, ST_LB1, ST_LB2, ST_LP0, ST_LP1, ST_LP2, ST_ATOMICS };
+enum { ST_BATCHES = 0, ST_CULLED, ST_POINTS, ST_LB0, ST_LB1, ST_LB2, ST_LP0, ST_LP1, ST_LP2, ST_ATOMICS, ST_WORDS };
 
 // A batch that survived culling, with everything its workgroup needs
 // (written by the classify kernel, read with scalar loads by the render kernel).
@@ -174,7 +174,7 @@ struct RasterShape {
 // The compiled shapes: X(waves, depth, tile).  The first is the default.
 #define PR_RASTER_SHAPES(X)                                                                                  \
   X(4, 5, 4096) X(4, 3, 4096) X(4, 4, 4096) X(4, 6, 4096) X(4, 5, 2048) X(2, 5, 2048) X(2, 5, 4096)        \
-  X(8, 5, 8192) X(1, 5, 1024) X(16, 5, 16384) X(16, 4, 16384) X(8, 5, 16384)
+  X(8, 5, 8192) X(1, 5, 1024) X(16, 5, 16384) X(16, 4, 16384) X(8, 5, 16384) X(4, 1, 4096)
 #define PR_SHAPE_NAME_(W_, D_, T_) raster_shape_w##W_##_d##D_##_t##T_
 #define PR_SHAPE_NAME(W_, D_, T_) PR_SHAPE_NAME_(W_, D_, T_)
 #define PR_DECLARE_SHAPE(W_, D_, T_) const RasterShape* PR_SHAPE_NAME_(W_, D_, T_)();

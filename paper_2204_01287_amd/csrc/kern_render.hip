@@ -275,6 +275,8 @@ __global__ void __launch_bounds__(256) k_classify(RenderArgs a) {
         if (lb[q]) atomicAdd((unsigned long long*)&a.stats[ST_LB0 + q], (unsigned long long)lb[q]);
         if (lp[q]) atomicAdd((unsigned long long*)&a.stats[ST_LP0 + q], (unsigned long long)lp[q]);
       }
+      const unsigned long long words = 4ull * lp[0] + 8ull * lp[1] + 12ull * lp[2];
+      if (words) atomicAdd((unsigned long long*)&a.stats[ST_WORDS], words);
     }
   }
   // tiled batches from the front of the list, untiled ones from the back, and
@@ -307,7 +309,8 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
   const bool valid = b < a.nb;
   uint64_t mask = 0;
   bool tiled_any = false;
-  uint64_t nculled = 0, pts = 0, lp[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+  int lmax = -1;  // highest level index among the live views (the words the run streams)
+  uint64_t nculled = 0, pts = 0, lp[3] = {0, 0, 0}, lb[3] = {0, 0, 0}, words = 0;
   if (valid) {
     const BatchRec rec = a.batches[b];
     for (uint32_t v = 0; v < a.nchunk; ++v) {
@@ -319,6 +322,7 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
         a.sub[(uint64_t)b * a.nviews + a.view0 + v] = out;
         mask |= 1ull << v;
         tiled_any = tiled_any || ((out.mode >> 16) & 1u);
+        lmax = li > lmax ? li : lmax;
         if constexpr (CNT) {
           pts += rec.count;
           lp[li] += rec.count;
@@ -327,6 +331,7 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
       }
       if constexpr (CNT) nculled += culled ? 1u : 0u;
     }
+    if (lmax >= 0) words = 4ull * (uint64_t)(lmax + 1) * rec.count;
   }
   if constexpr (CNT) {
     uint64_t nbv = valid ? a.nchunk : 0u;
@@ -334,6 +339,7 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
       nbv += __shfl_xor(nbv, o);
       nculled += __shfl_xor(nculled, o);
       pts += __shfl_xor(pts, o);
+      words += __shfl_xor(words, o);
       for (int q = 0; q < 3; ++q) {
         lp[q] += __shfl_xor(lp[q], o);
         lb[q] += __shfl_xor(lb[q], o);
@@ -347,6 +353,7 @@ __global__ void __launch_bounds__(256) k_classify_views(ClassifyViewsArgs a) {
         if (lb[q]) atomicAdd((unsigned long long*)&a.stats[ST_LB0 + q], (unsigned long long)lb[q]);
         if (lp[q]) atomicAdd((unsigned long long*)&a.stats[ST_LP0 + q], (unsigned long long)lp[q]);
       }
+      if (words) atomicAdd((unsigned long long*)&a.stats[ST_WORDS], (unsigned long long)words);
     }
   }
   const bool live = mask != 0, direct = live && !tiled_any;

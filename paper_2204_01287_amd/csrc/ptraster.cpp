@@ -673,6 +673,7 @@ pr_status pr_get_stats(pr_ctx* ctx, pr_stats* out) {
     out->level_points[i] = st[ptr::ST_LP0 + i];
   }
   out->atomics = st[ptr::ST_ATOMICS];
+  out->words_bytes = st[ptr::ST_WORDS];
   return PR_OK;
 }
 

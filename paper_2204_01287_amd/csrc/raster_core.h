@@ -208,6 +208,7 @@ __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const
       if constexpr (BAND) ok[j] = ok[j] && (ly < L.th);
       key[j] = make_key(p.hw, i0 + j);
       ad[j] = __umul24(ly, L.tw8) + (lx << 3);
+      asm volatile("" : "+v"(ad[j]));  // kept for the atomic, not recomputed
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -273,16 +274,44 @@ struct Streams {
   const uint32_t* colors;  // shading pass only
 };
 
+// The streams of one batch as buffer resources based at its first point: a
+// group's 16-byte word of a lane is then at the lane's constant offset
+// lane * 16 plus the group's uniform offset g * 1024, so loads need no vector
+// address arithmetic.  A batch of up to 2^22 groups (2^30 points) fits the
+// 32-bit offsets; raster_points cuts longer batches into such chunks.
+struct BatchStreams {
+  __amdgpu_buffer_rsrc_t l, m, h, c;
+};
+constexpr uint32_t RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer (gfx9 family)
+constexpr uint32_t CHUNK_POINTS = 1u << 30;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const uint32_t* s, uint32_t first) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(s + first), (short)0, -1, RSRC_WORD3);
+}
+template <int K, bool ACC>
+__device__ __forceinline__ BatchStreams batch_streams(const Streams& a, uint32_t first) {
+  BatchStreams b;
+  b.l = stream_rsrc(a.low, first);
+  if constexpr (K >= 20) b.m = stream_rsrc(a.med, first);
+  if constexpr (K == 30) b.h = stream_rsrc(a.high, first);
+  if constexpr (ACC) b.c = stream_rsrc(a.colors, first);
+  return b;
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 buf16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <int K, bool ACC = false>
-__device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, uint32_t g, uint32_t lane) {
-  const uint32_t q = first / 4 + g * 64 + lane;  // first is a multiple of 4
+__device__ __forceinline__ Words load_group(const BatchStreams& b, uint32_t g, uint32_t lane16) {
+  const uint32_t go = g * 1024u;
   Words w;
-  w.l = reinterpret_cast<const uint4*>(a.low)[q];
-  if constexpr (K >= 20) w.m = reinterpret_cast<const uint4*>(a.med)[q];
+  w.l = buf16(b.l, lane16, go);
+  if constexpr (K >= 20) w.m = buf16(b.m, lane16, go);
   else w.m = make_uint4(0, 0, 0, 0);
-  if constexpr (K == 30) w.h = reinterpret_cast<const uint4*>(a.high)[q];
+  if constexpr (K == 30) w.h = buf16(b.h, lane16, go);
   else w.h = make_uint4(0, 0, 0, 0);
-  if constexpr (ACC) w.c = reinterpret_cast<const uint4*>(a.colors)[q];
+  if constexpr (ACC) w.c = buf16(b.c, lane16, go);
   else w.c = make_uint4(0, 0, 0, 0);
   return w;
 }
@@ -292,43 +321,50 @@ __device__ __forceinline__ Words load_group(const Streams& a, uint32_t first, ui
 // 16-byte load per word).  The ragged tail goes to wave ngrp mod WAVES, the
 // next in that rotation (one of the waves with the fewest groups).
 template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
-__device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
-                              uint32_t wave, uint32_t lane, uint32_t& natom) {
+__device__ void raster_chunk(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
+                             uint32_t wave, uint32_t lane, uint32_t& natom) {
+  const BatchStreams bs = batch_streams<K, ACC>(a, first);
+  const uint32_t lane16 = lane * 16u;
+  // The rare SLOW class (binary64 floor) keeps one group in flight and the
+  // rare 20- and 30-bit batches (two and three words per point) at most
+  // three: deeper prefetch there would set the register count of the whole
+  // kernel, which the 10-bit loops (almost every point) then pay for.
+  constexpr int PF = CLS == CLS_SLOW ? 1 : (K == 10 ? PREFETCH : (PREFETCH < 3 ? PREFETCH : 3));
   const uint32_t ngrp = count >> 8;
   const uint32_t nj = wave < ngrp ? (ngrp - wave + WAVES - 1) / WAVES : 0;  // this wave's groups
   if (nj > 0) {
-    // PREFETCH register sets rotate through the wave's groups; each is
-    // reloaded in place right after use, so every load is issued PREFETCH
+    // PF register sets rotate through the wave's groups; each is
+    // reloaded in place right after use, so every load is issued PF
     // groups ahead of its use.  The rounds are branch-free: reloads are
     // unconditional and clamped to the wave's last group, so every wait
     // counts exactly the loads in flight.  Only whole rounds run this way;
-    // the last nj mod PREFETCH groups are then already loaded in the first
+    // the last nj mod PF groups are then already loaded in the first
     // register sets and are processed without reloads (no empty slots).
     const uint32_t glast = wave + (nj - 1) * WAVES;
-    Words R[PREFETCH];
-    uint32_t gi[PREFETCH];
+    Words R[PF];
+    uint32_t gi[PF];
 #pragma unroll
-    for (int d = 0; d < PREFETCH; ++d) {
+    for (int d = 0; d < PF; ++d) {
       gi[d] = wave + d * WAVES;
-      R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
+      R[d] = load_group<K, ACC>(bs, min(gi[d], glast), lane16);
       // keep the initial loads in the order of their use, the order the
-      // loop reissues them in: the loop's waits then count PREFETCH - 1
+      // loop reissues them in: the loop's waits then count PF - 1
       // younger loads on every path
       __builtin_amdgcn_sched_barrier(0);
     }
-    const uint32_t whole = nj - nj % PREFETCH;
-    for (uint32_t j = 0; j < whole; j += PREFETCH) {
+    const uint32_t whole = nj - nj % PF;
+    for (uint32_t j = 0; j < whole; j += PF) {
 #pragma unroll
-      for (int d = 0; d < PREFETCH; ++d) {
+      for (int d = 0; d < PF; ++d) {
         const uint32_t g = gi[d];  // <= glast in every whole round
         four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + g * 256 + lane * 4, 4u, natom);
-        gi[d] = g + PREFETCH * WAVES;
-        R[d] = load_group<K, ACC>(a, first, min(gi[d], glast), lane);
+        gi[d] = g + PF * WAVES;
+        R[d] = load_group<K, ACC>(bs, min(gi[d], glast), lane16);
       }
     }
     const uint32_t rest = nj - whole;  // groups gi[0 .. rest - 1], loaded in R[0 .. rest - 1]
 #pragma unroll
-    for (int d = 0; d < PREFETCH; ++d)
+    for (int d = 0; d < PF; ++d)
       if ((uint32_t)d < rest)
         four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + gi[d] * 256 + lane * 4, 4u, natom);
   }
@@ -352,6 +388,17 @@ __device__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, u
     t.h = make_uint4(h[0], h[1], h[2], h[3]);
     t.c = make_uint4(c[0], c[1], c[2], c[3]);
     four_points<K, CLS, TILED, ACC, BAND>(L, tile, t, first + j0, nv, natom);
+  }
+}
+
+// A batch, in chunks of at most CHUNK_POINTS points (one chunk for every
+// batch of a regular build).
+template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
+__device__ __forceinline__ void raster_points(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first,
+                                              uint32_t count, uint32_t wave, uint32_t lane, uint32_t& natom) {
+  for (uint32_t c0 = 0; c0 < count; c0 += CHUNK_POINTS) {
+    const uint32_t n = count - c0 < CHUNK_POINTS ? count - c0 : CHUNK_POINTS;
+    raster_chunk<K, CLS, TILED, ACC, BAND>(L, a, tile, first + c0, n, wave, lane, natom);
   }
 }
 
@@ -491,7 +538,7 @@ __device__ __forceinline__ void add_atomics(uint64_t* stats, uint32_t natom, uin
 // render kernels' template arguments only so that profiles name the shape
 // that ran; it must equal the translation unit's shape.
 template <bool CNT, int SW, int SD, int ST>
-__global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_render(RenderArgs a) {
   static_assert(SW == WAVES && SD == PREFETCH && ST == (int)TILE_MAX, "shape tag");
   __shared__ uint64_t tile[TILE_MAX];
   __shared__ uint32_t s_next;
@@ -520,7 +567,7 @@ __global__ void __launch_bounds__(THREADS) k_render(RenderArgs a) {
 // views); the workgroup renders the batch once per view, so its coordinate
 // words come from HBM once and from the caches for the further views.
 template <bool CNT, int SW, int SD, int ST>
-__global__ void __launch_bounds__(THREADS) k_render_views(RenderViewsArgs a) {
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_render_views(RenderViewsArgs a) {
   static_assert(SW == WAVES && SD == PREFETCH && ST == (int)TILE_MAX, "shape tag");
   __shared__ uint64_t tile[TILE_MAX];
   __shared__ uint32_t s_next;

@@ -2,8 +2,10 @@
 
 A request names a resident cloud, a camera and an image size, and arrives at some time.  The scheduler loop:
 
-  * admits arrived requests in arrival order while the bytes of their visibility buffer and framebuffer
-    (12 bytes per pixel) fit the memory budget (a request larger than the whole budget runs alone);
+  * admits arrived requests in arrival order while their device bytes fit the memory budget (a request larger
+    than the whole budget runs alone): its visibility buffer and framebuffer (12 bytes per pixel) and its share of
+    the multi-view work area of the group that will carry it (pr_views_work_bytes of one view of its cloud, which
+    bounds the share: a group's work area is its header and runs plus 80 bytes per batch and view);
   * keeps the admitted requests that are not yet on the GPU per cloud, and whenever a HIP stream has fewer than
     `depth` groups in flight, launches the cloud with the oldest waiting request as one group on it: one
     pr_render_views launch for up to PR_MAX_VIEWS of that cloud's waiting requests (the batches' coordinate words
@@ -134,10 +136,12 @@ class Server:
                  max_group: int = B.PR_MAX_VIEWS, clear_rgba: int = 0xFF000000, on_result=None, depth: int = 1):
         import torch
 
-        self.scheduler = Scheduler(nstreams, budget_bytes, max_group, depth, self.request_bytes)
         self.torch = torch
         self.device = device
         self.handles = [getattr(c, "handle", c) for c in clouds]
+        # a request's bound on its share of the work area of a pr_render_views group over its cloud
+        self.work_share = [B.pr_views_work_bytes(h, 1) for h in self.handles]
+        self.scheduler = Scheduler(nstreams, budget_bytes, max_group, depth, self.request_bytes)
         self.streams = [torch.cuda.Stream(device) for _ in range(nstreams)]
         self.ctxs = [B.Context(device, stream=s) for s in self.streams]
         self.clear_rgba = clear_rgba
@@ -147,9 +151,9 @@ class Server:
     def peak_bytes(self) -> int:
         return self.scheduler.peak_bytes
 
-    @staticmethod
-    def request_bytes(r: Request) -> int:
-        return 12 * r.cam.width * r.cam.height
+    def request_bytes(self, r: Request) -> int:
+        """Device bytes a request holds while admitted: visibility buffer + framebuffer + its work-area share."""
+        return 12 * r.cam.width * r.cam.height + self.work_share[r.cloud]
 
     def _launch(self, si: int, cloud: int, group):
         torch = self.torch

@@ -76,6 +76,21 @@ def _check(ctx, dc, B, cams, mode="adaptive"):
             tot[k] = [a + b for a, b in zip(tot[k], s[k])]
     for k in tot:
         assert st[k] == tot[k], (k, st[k], tot[k])
+    # coordinate words the frame streams: per batch and classify launch (16 views), at the highest level among
+    # the batch's live views there (the oracle's per-batch decisions)
+    words = 0
+    count = B.batches["count"].astype(np.uint64)
+    for c0 in range(0, len(cams), 16):
+        lmax = np.zeros(len(B.batches), np.int64)
+        for c in cams[c0:c0 + 16]:
+            d = oracle.decide_all(B.batches, c.view, c.proj, c.width, c.height, o)
+            lv = np.where(d["culled"] == 0, d["level"] // 10, 0)
+            lmax = np.maximum(lmax, lv)
+        words += int((4 * lmax.astype(np.uint64) * count).sum())
+    assert st["words_bytes"] == words, (st["words_bytes"], words)
+    _, _, s1 = gpu_render(ctx, dc, cams[0].view, cams[0].proj, cams[0].width, cams[0].height, counters=1, **opt)
+    lp = s1["level_points"]
+    assert s1["words_bytes"] == 4 * lp[0] + 8 * lp[1] + 12 * lp[2]
     return vbs
 
 

@@ -47,7 +47,7 @@ def ctx():
     c.close()
 
 
-def _bench_frame(ctx, handle, cam):
+def _bench_frame(ctx, handle, cam, precision=0):
     """One eye exactly as bench.py times it; returns host copies of VB and FB and the frame counters."""
     import torch
     import paper_2204_01287_amd as pr
@@ -56,23 +56,25 @@ def _bench_frame(ctx, handle, cam):
     vb = torch.empty(cam.width * cam.height, dtype=torch.int64, device=dev)
     fb = torch.empty(cam.width * cam.height, dtype=torch.int32, device=dev)
     vb.fill_(7)  # stale contents: the frame must clear them
-    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height, None, vb)
+    o = pr.RenderOpts.make(precision=precision) if precision else None
+    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height, o, vb)
     pr.pr_resolve(ctx.handle, handle, vb, cam.width, cam.height, CLEAR, fb)
     pr.pr_sync(ctx.handle)
     out_vb, out_fb = vb.cpu().numpy().view(np.uint64), fb.cpu().numpy().view(np.uint32)
     # the counters frame (bench.py's untimed first frame)
-    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height, pr.RenderOpts.make(counters=1), vb)
+    pr.pr_render(ctx.handle, handle, cam.view, cam.proj, cam.width, cam.height,
+                 pr.RenderOpts.make(precision=precision, counters=1), vb)
     st = pr.pr_get_stats(ctx.handle)
     assert np.array_equal(vb.cpu().numpy().view(np.uint64), out_vb), "counters frame differs from the timed frame"
     return out_vb, out_fb, st
 
 
-def _check_eye(ctx, handle, built, colors, cam, nb, tag):
+def _check_eye(ctx, handle, built, colors, cam, nb, tag, precision=0):
     t0 = _t()
-    say(f"{tag}: bench frame on the GPU ({cam.width}x{cam.height})")
-    vb, fb, st = _bench_frame(ctx, handle, cam)
+    say(f"{tag}: bench frame on the GPU ({cam.width}x{cam.height}, precision {precision or 'adaptive'})")
+    vb, fb, st = _bench_frame(ctx, handle, cam, precision)
     say(f"{tag}: GPU frame done ({_t() - t0:.1f} s); oracle render of {nb} batches on {RENDER_WORKERS} threads")
-    ref, st_ref = oracle_frame(built, cam, nb)
+    ref, st_ref = oracle_frame(built, cam, nb, oracle.opts(precision=precision))
     say(f"{tag}: oracle done ({_t() - t0:.1f} s): {st_ref}")
     assert_vb_equal(vb, ref, cam.width)
     assert np.array_equal(fb, oracle.resolve(ref, colors, CLEAR)), "framebuffer differs"
@@ -125,6 +127,50 @@ def test_c2_build_full(c2):
 def test_c2_orbit_frame(ctx, c2, frame):
     cam = c2.wl["cams"][frame]
     _check_eye(ctx, c2.cloud["handle"], c2.B, c2.B.colors, cam, c2.nb, f"C2 orbit view {frame}")
+
+
+def test_c2_force30_frames(ctx, c2):
+    """Fixed 12-byte loads (PR_FORCE30, Sec. 3.3's comparison), as bench.py's c2 leg renders them."""
+    import synth
+
+    for f in (0, 30):
+        cam = synth.orbit_camera(f)
+        _check_eye(ctx, c2.cloud["handle"], c2.B, c2.B.colors, cam, c2.nb, f"C2 orbit {f} FORCE30", precision=30)
+
+
+@pytest.fixture(scope="module")
+def c2_generation(ctx):
+    """The same 1e8 points batched in their generation order (no Morton sort), as bench.py's c2 leg builds them."""
+    import torch
+    import bench
+
+    wl = dict(bench.workload("c2", None), morton=False, name="terrain_1e8_generation")
+    seen = {}
+
+    def keep(lo, hi, xyz, rgba):
+        seen["xyz"], seen["rgba"] = xyz, rgba
+
+    say("C2 generation order: build on the GPU")
+    cloud = bench.load_cloud(ctx, wl, on_chunk=keep)
+    B = oracle.build_cloud(seen["xyz"], seen["rgba"], S, morton=False)
+    yield types.SimpleNamespace(wl=wl, cloud=cloud, B=B, n=wl["n"], nb=cloud["nb"])
+    import paper_2204_01287_amd as pr
+
+    pr.pr_cloud_free(cloud["handle"])
+    cloud.clear()
+    torch.cuda.empty_cache()
+
+
+def test_c2_generation_order(ctx, c2_generation):
+    import synth
+
+    g = c2_generation
+    v = device_views(g.cloud, g.n, g.nb)
+    for f in ("colors", "low", "med", "high"):
+        assert np.array_equal(_u32(getattr(v, f)), getattr(g.B, f)), f"{f} differs"
+    assert np.array_equal(v.batches.cpu().numpy(), g.B.batches.view(np.uint8)), "batch records differ"
+    for f in (0, 45):
+        _check_eye(ctx, g.cloud["handle"], g.B, g.B.colors, synth.orbit_camera(f), g.nb, f"C2 generation order {f}")
 
 
 # =================================================================== C3: 2e9
@@ -197,18 +243,21 @@ def test_c3_stereo_one_launch(ctx, c3):
     oracle_stats_match(st, tot)
 
 
-def test_c3_hqs_eye0(ctx, c3):
-    """High-quality shading of eye 0: sums and averaged framebuffer equal the oracle's (threads over interleaved
-    batch sets, private sums added modulo 2^64, exact)."""
+@pytest.mark.parametrize("eye", [0, 1])
+def test_c3_hqs(ctx, c3, eye):
+    """High-quality shading of each eye, as bench.py's shading leg renders them: visibility buffer, sums and
+    averaged framebuffer equal the oracle's (threads over interleaved batch sets, private sums added modulo 2^64,
+    exact)."""
     import torch
     import paper_2204_01287_amd as pr
 
-    cam = c3.wl["cams"][0]
+    cam = c3.wl["cams"][eye]
     w, h = cam.width, cam.height
     vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
     acc = torch.empty(2 * w * h, dtype=torch.int64, device="cuda")
     fb = torch.empty(w * h, dtype=torch.int32, device="cuda")
-    say("C3: high-quality shading of eye 0")
+    acc.fill_(5)  # stale sums: the frame must clear them
+    say(f"C3: high-quality shading of eye {eye}")
     pr.pr_render_hqs(ctx.handle, c3.cloud["handle"], cam.view, cam.proj, w, h, None, 1.01, vb, acc, CLEAR, fb)
     pr.pr_sync(ctx.handle)
     ref, _ = oracle_frame(c3.built, cam, c3.nb)
@@ -223,5 +272,6 @@ def test_c3_hqs_eye0(ctx, c3):
     with ThreadPoolExecutor(RENDER_WORKERS) as ex:
         for part in ex.map(job, groups):
             racc += part
+    assert np.count_nonzero(racc) > 0
     assert np.array_equal(acc.cpu().numpy().view(np.uint64), racc)
     assert np.array_equal(fb.cpu().numpy().view(np.uint32), oracle.resolve_hqs(racc, CLEAR))

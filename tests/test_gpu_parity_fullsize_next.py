@@ -4,8 +4,9 @@ C4 -- 500,000,000-point terrain (seed 4, index order, Morton build, 10,240 point
 1024 x 1024 (synth.camera_array).  The device's Morton build is checked against the oracle chunk by chunk as for C3
 (the permutation is proved to be the unique stable order; positions, colours, batch records and Eq. 1 words are
 the oracle's).  The frame is bench.py's: pr_autotune over the 64-view frame, then all 64 views in one
-pr_render_views launch under the winning tuning.  The four views that cover the most pixels equal the oracle's
-renders pixel for pixel; every other view equals its single-view render under the default tuning.
+pr_render_views launch under the winning tuning.  Every one of the 64 views equals the oracle's render pixel for
+pixel (threaded oracle, interleaved batch sets merged by elementwise minimum), and also its single-view render under
+the default tuning.
 
 C6 -- the 500,000,000-point terrain (seed 3, index order) converted to a layered point cloud (seed 7, batches of at
 most 10,240 points, 227,804 variable-size batches), as bench.py's LOD leg.  The spans build (batch records, Eq. 1
@@ -100,21 +101,20 @@ def test_c4_camera_array_autotuned_one_launch(ctx, c4):
     pr.pr_render_views(ctx.handle, h, views, None, work, need)
     pr.pr_sync(ctx.handle)
     got = [vb.cpu().numpy().view(np.uint64).copy() for vb in vbs]
-    # the four views that see the most of the terrain (a camera near the edge may look at nothing)
     covered = [int(np.count_nonzero(g != oracle.EMPTY)) for g in got]
-    sampled = sorted(np.argsort(covered)[-4:].tolist())
-    say(f"C4: views {sampled} against the oracle (covered pixels {[covered[i] for i in sampled]})")
-    for i in sampled:
-        t0 = _t()
-        ref, _ = oracle_frame(c4.built, cams[i], c4.nb)
-        say(f"C4: view {i} oracle done ({_t() - t0:.1f} s)")
-        assert_vb_equal(got[i], ref, cams[i].width)
-        assert np.count_nonzero(ref != oracle.EMPTY) > 0
+    say(f"C4: all 64 views against the oracle (covered pixels: min {min(covered)}, max {max(covered)})")
+    t0 = _t()
+    seen = 0
+    for i, cam in enumerate(cams):
+        ref, _ = oracle_frame(c4.built, cam, c4.nb)
+        assert_vb_equal(got[i], ref, cam.width)
+        seen += int(np.count_nonzero(ref != oracle.EMPTY) > 0)
+        if i % 8 == 7:
+            say(f"C4: {i + 1} views equal the oracle ({_t() - t0:.1f} s)")
+    assert seen >= 32, "most cameras of the array must see the terrain"
     pr.pr_set_tuning(ctx.handle)
     one = torch.empty(1024 * 1024, dtype=torch.int64, device="cuda")
     for i, c in enumerate(cams):
-        if i in sampled:
-            continue
         pr.pr_render(ctx.handle, h, c.view, c.proj, c.width, c.height, None, one)
         pr.pr_sync(ctx.handle)
         assert np.array_equal(one.cpu().numpy().view(np.uint64), got[i]), f"view {i} differs from its single render"

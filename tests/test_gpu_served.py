@@ -52,7 +52,7 @@ def test_served_results_equal_solo_renders():
     srv.close()
     assert sorted(d.rid for d in done) == list(range(len(reqs)))
     assert max(d.group for d in done) > 1, "no request shared a launch"
-    assert srv.peak_bytes <= max(budget, max(Server.request_bytes(r) for r in reqs))
+    assert srv.peak_bytes <= max(budget, max(srv.request_bytes(r) for r in reqs))
     assert all(d.completed >= d.launched >= d.arrival - 1e-6 for d in done)
     assert len({d.stream for d in done}) > 1
 
