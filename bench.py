@@ -660,8 +660,9 @@ class _Keep:
 def c2_leg(pr, ctx, steps: int, warmup: int, n: int = 100_000_000):
     """The paper's bandwidth and ordering comparisons on the 1e8-point terrain, over the 60-frame orbit at
     1920x1080 (per frame: pr_render + pr_resolve): adaptive precision (4/8/12-byte loads, Sec. 3.3) against fixed
-    12-byte loads (PR_FORCE30), Morton order against the generation order (10 m tiles in serpentine strips,
-    Sec. 4.2), and the default prefetch depth against one group in flight per wave (Sec. 3.4).  Every variant
+    12-byte loads (PR_FORCE30), Morton order against the generation order (10 m tiles in serpentine strips) and
+    against the generator's index order (spatially incoherent, Sec. 4.2), and the default prefetch depth against
+    one group in flight per wave (Sec. 3.4).  Every variant
     renders the same points; only what each frame loads, in which order, and how far ahead, differs."""
     import numpy as np
     import torch
@@ -674,16 +675,19 @@ def c2_leg(pr, ctx, steps: int, warmup: int, n: int = 100_000_000):
               sh["tile_px"] == shapes[0]["tile_px"])
     clouds = {}
     t0 = time.perf_counter()
-    for order, morton in (("morton", True), ("generation", False)):
+    # generation order: 10 m tiles in serpentine strips (aerial-strip-like, already compact batches); index order:
+    # the generator's points by index, spatially incoherent (like the paper's scan order of laser scans)
+    for order, morton, gen in (("morton", True, 1), ("generation", False, 1), ("index", False, 0)):
         clouds[order] = load_cloud(ctx, dict(name=f"terrain_1e8_{order}", seed=synth.C2_SEED, n=n, morton=morton,
-                                             order=1))
-    log(f"c2: two 1e8-point builds in {time.perf_counter() - t0:.1f} s")
+                                             order=gen))
+    log(f"c2: three 1e8-point builds in {time.perf_counter() - t0:.1f} s")
     w, h = cams[0].width, cams[0].height
     vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
     fb = torch.empty(w * h, dtype=torch.int32, device="cuda")
     variants = {"morton_adaptive": ("morton", pr.PR_ADAPTIVE, 0),
                 "morton_force30": ("morton", pr.PR_FORCE30, 0),
                 "generation_adaptive": ("generation", pr.PR_ADAPTIVE, 0),
+                "index_order_adaptive": ("index", pr.PR_ADAPTIVE, 0),
                 "morton_adaptive_prefetch1": ("morton", pr.PR_ADAPTIVE, d1)}
     out = {"points": n, "frames": 60, "view": f"{w}x{h}", "prefetch1_shape": shapes[d1]}
     for name, (order, prec, shape) in variants.items():
@@ -723,6 +727,7 @@ def c2_leg(pr, ctx, steps: int, warmup: int, n: int = 100_000_000):
     base = out["morton_adaptive"]["ms_per_frame"]
     out["speedup_adaptive_vs_force30"] = round(out["morton_force30"]["ms_per_frame"] / base, 3)
     out["speedup_morton_vs_generation"] = round(out["generation_adaptive"]["ms_per_frame"] / base, 3)
+    out["speedup_morton_vs_index_order"] = round(out["index_order_adaptive"]["ms_per_frame"] / base, 3)
     out["speedup_prefetch_vs_depth1"] = round(out["morton_adaptive_prefetch1"]["ms_per_frame"] / base, 3)
     pr.pr_sync(ctx.handle)
     for c in clouds.values():

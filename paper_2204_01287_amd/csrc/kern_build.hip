@@ -188,15 +188,30 @@ __global__ void __launch_bounds__(256) k_scan_apply(uint32_t* __restrict__ x, ui
   }
 }
 
+// Scatter of one pass: the tile is first ranked stably into LDS, ordered by
+// digit (equal digits in input order: wave ballots give the rank inside a
+// wave, LDS counters carry it across waves and chunks), then written out from
+// LDS so that consecutive threads write consecutive slots of one digit's
+// range: the tile's elements of a digit (about RS_TILE / 256) leave as one run
+// instead of one scattered 8-byte store each.
 __global__ void __launch_bounds__(256) k_radix_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                        uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                        uint64_t n, int shift, const uint32_t* __restrict__ offs,
                                                        uint64_t nblk) {
-  __shared__ uint32_t goff[256];
+  __shared__ uint64_t skey[RS_TILE];
+  __shared__ uint32_t sval[RS_TILE];
+  __shared__ uint32_t goff[256];    // first output slot of this tile's digit d
+  __shared__ uint32_t tstart[256];  // first LDS slot of digit d in the tile
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[4][256];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  goff[tid] = offs[(uint64_t)tid * nblk + blockIdx.x];
+  const uint64_t m = 256 * nblk;
+  const uint64_t at = (uint64_t)tid * nblk + blockIdx.x;  // (digit tid, this block) in the digit-major scan
+  const uint32_t g0 = offs[at];
+  const uint32_t g1 = at + 1 < m ? offs[at + 1] : (uint32_t)n;  // next (digit, block) starts where this ends
+  goff[tid] = g0;
+  uint32_t total;
+  tstart[tid] = block_exclusive_scan(g1 - g0, &total);
   run[tid] = 0;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
@@ -215,23 +230,33 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint64_t* __restric
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
       const bool set = (d >> bit) & 1u;
-      const uint64_t m = __ballot(set);
-      peers &= set ? m : ~m;
+      const uint64_t mk = __ballot(set);
+      peers &= set ? mk : ~mk;
     }
     const uint32_t rank = __popcll(peers & lt_mask);
     if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = goff[d] + run[d] + rank;
+      uint32_t pos = tstart[d] + run[d] + rank;
       for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      if (pos < n) {  // always true for a consistent histogram; never write outside
-        kout[pos] = key;
-        vout[pos] = val;
+      if (pos < RS_TILE) {  // always true for a consistent histogram; never write outside
+        skey[pos] = key;
+        sval[pos] = val;
       }
     }
     __syncthreads();
     run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-    __syncthreads();
+  }
+  __syncthreads();
+  const uint32_t nt = total < (uint32_t)RS_TILE ? total : (uint32_t)RS_TILE;
+  for (uint32_t p = tid; p < nt; p += RS_THREADS) {
+    const uint64_t key = skey[p];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint64_t pos = (uint64_t)goff[d] + (p - tstart[d]);
+    if (pos < n) {  // always true for a consistent histogram; never write outside
+      kout[pos] = key;
+      vout[pos] = sval[p];
+    }
   }
 }
 

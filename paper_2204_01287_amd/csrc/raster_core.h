@@ -59,6 +59,7 @@ struct Loop {
   uint32_t cx, cy;  // 0x4B000000 + tile origin (x0, y0), in VGPRs: pixel_fast yields tile coordinates
   uint32_t tw, th;  // tile rectangle size (tiled batches)
   uint32_t tw8;     // tile row pitch in bytes
+  uint32_t base8;   // byte offset of this view's sub-tile in the LDS tile (two-view passes)
   uint64_t* vb;
   // high-quality shading pass only
   float window;     // depth window factor
@@ -266,6 +267,65 @@ __device__ __forceinline__ void four_points(const Loop& L, uint64_t* tile, const
   }
 }
 
+// Two views in one pass (multi-view frames): four consecutive 10-bit points
+// of one lane, decoded once, projected into view A and view B and combined in
+// each view's LDS sub-tile exactly as four_points does for one view.  Both
+// views' batch records are tiled, unbanded and INSIDE (CA/CB = CLS_INSIDE) or
+// PARTIAL.
+template <int CA, int CB>
+__device__ __forceinline__ void four_points_pair(const Loop& A, const Loop& B, uint64_t* tile, const Words& w,
+                                                 uint32_t i0, uint32_t nvalid) {
+  const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
+  uint8_t* const tb = reinterpret_cast<uint8_t*>(tile);
+  uint32_t ad[8];
+  uint64_t key[8], old[8];
+  bool ok[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float X, Y, Z;
+    decode<10>(Lw[j], 0u, 0u, X, Y, Z);
+    const uint32_t idx = i0 + j;
+    {
+      const Proj p = project(A, X, Y, Z);
+      ok[j] = (uint32_t)j < nvalid;
+      if constexpr (CA != CLS_INSIDE) ok[j] = ok[j] && visible(A, p);
+      uint32_t lx, ly;
+      pixel_fast(p, A.cx, A.cy, lx, ly);
+      key[j] = make_key(p.hw, idx);
+      ad[j] = __umul24(ly, A.tw8) + (lx << 3);
+      asm volatile("" : "+v"(ad[j]));
+    }
+    {
+      const Proj p = project(B, X, Y, Z);
+      ok[4 + j] = (uint32_t)j < nvalid;
+      if constexpr (CB != CLS_INSIDE) ok[4 + j] = ok[4 + j] && visible(B, p);
+      uint32_t lx, ly;
+      pixel_fast(p, B.cx, B.cy, lx, ly);
+      key[4 + j] = make_key(p.hw, idx);
+      ad[4 + j] = __umul24(ly, B.tw8) + ((lx << 3) + B.base8);
+      asm volatile("" : "+v"(ad[4 + j]));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const bool inside = j < 4 ? CA == CLS_INSIDE : CB == CLS_INSIDE;
+    if (inside) {
+      old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      old[j] = 0;
+      if (ok[j])
+        old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (ok[j] && key[j] < old[j])
+      __hip_atomic_fetch_min(reinterpret_cast<uint64_t*>(tb + ad[j]), key[j], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // The coordinate streams of the cloud (low, medium, high words).
 struct Streams {
   const uint32_t* low;
@@ -318,18 +378,15 @@ __device__ __forceinline__ Words load_group(const BatchStreams& b, uint32_t g, u
 
 // The points of one batch, split over the workgroup's waves: wave w takes the
 // groups of 256 points w, w + WAVES, ... (4 consecutive points per lane, one
-// 16-byte load per word).  The ragged tail goes to wave ngrp mod WAVES, the
-// next in that rotation (one of the waves with the fewest groups).
-template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
-__device__ void raster_chunk(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first, uint32_t count,
-                             uint32_t wave, uint32_t lane, uint32_t& natom) {
+// 16-byte load per word) and hands each lane's four points to
+// fn(words, index of the first, number valid).  The ragged tail goes to wave
+// ngrp mod WAVES, the next in that rotation (one of the waves with the fewest
+// groups).  PF groups are in flight per wave.
+template <int K, bool ACC, int PF, typename Fn>
+__device__ __forceinline__ void stream_chunk(const Streams& a, uint32_t first, uint32_t count, uint32_t wave,
+                                             uint32_t lane, Fn&& fn) {
   const BatchStreams bs = batch_streams<K, ACC>(a, first);
   const uint32_t lane16 = lane * 16u;
-  // The rare SLOW class (binary64 floor) keeps one group in flight and the
-  // rare 20- and 30-bit batches (two and three words per point) at most
-  // three: deeper prefetch there would set the register count of the whole
-  // kernel, which the 10-bit loops (almost every point) then pay for.
-  constexpr int PF = CLS == CLS_SLOW ? 1 : (K == 10 ? PREFETCH : (PREFETCH < 3 ? PREFETCH : 3));
   const uint32_t ngrp = count >> 8;
   const uint32_t nj = wave < ngrp ? (ngrp - wave + WAVES - 1) / WAVES : 0;  // this wave's groups
   if (nj > 0) {
@@ -357,7 +414,7 @@ __device__ void raster_chunk(const Loop& L, const Streams& a, uint64_t* tile, ui
 #pragma unroll
       for (int d = 0; d < PF; ++d) {
         const uint32_t g = gi[d];  // <= glast in every whole round
-        four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + g * 256 + lane * 4, 4u, natom);
+        fn(R[d], first + g * 256 + lane * 4, 4u);
         gi[d] = g + PF * WAVES;
         R[d] = load_group<K, ACC>(bs, min(gi[d], glast), lane16);
       }
@@ -365,8 +422,7 @@ __device__ void raster_chunk(const Loop& L, const Streams& a, uint64_t* tile, ui
     const uint32_t rest = nj - whole;  // groups gi[0 .. rest - 1], loaded in R[0 .. rest - 1]
 #pragma unroll
     for (int d = 0; d < PF; ++d)
-      if ((uint32_t)d < rest)
-        four_points<K, CLS, TILED, ACC, BAND>(L, tile, R[d], first + gi[d] * 256 + lane * 4, 4u, natom);
+      if ((uint32_t)d < rest) fn(R[d], first + gi[d] * 256 + lane * 4, 4u);
   }
   const uint32_t rem = count & 255u;
   if (rem && wave == ngrp % WAVES) {  // ragged tail of the batch: scalar loads, per-point bounds
@@ -387,8 +443,22 @@ __device__ void raster_chunk(const Loop& L, const Streams& a, uint64_t* tile, ui
     t.m = make_uint4(m[0], m[1], m[2], m[3]);
     t.h = make_uint4(h[0], h[1], h[2], h[3]);
     t.c = make_uint4(c[0], c[1], c[2], c[3]);
-    four_points<K, CLS, TILED, ACC, BAND>(L, tile, t, first + j0, nv, natom);
+    fn(t, first + j0, nv);
   }
+}
+
+// The points of one batch into one view (tile or visibility buffer).
+template <int K, int CLS, bool TILED, bool ACC = false, bool BAND = false>
+__device__ __forceinline__ void raster_chunk(const Loop& L, const Streams& a, uint64_t* tile, uint32_t first,
+                                             uint32_t count, uint32_t wave, uint32_t lane, uint32_t& natom) {
+  // The rare SLOW class (binary64 floor) keeps one group in flight and the
+  // rare 20- and 30-bit batches (two and three words per point) at most
+  // three: deeper prefetch there would set the register count of the whole
+  // kernel, which the 10-bit loops (almost every point) then pay for.
+  constexpr int PF = CLS == CLS_SLOW ? 1 : (K == 10 ? PREFETCH : (PREFETCH < 3 ? PREFETCH : 3));
+  stream_chunk<K, ACC, PF>(a, first, count, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+    four_points<K, CLS, TILED, ACC, BAND>(L, tile, w, i0, nv, natom);
+  });
 }
 
 // A batch, in chunks of at most CHUNK_POINTS points (one chunk for every
@@ -506,6 +576,82 @@ __device__ __forceinline__ void render_batch(const LiveBatch& rec, uint32_t W, u
   __syncthreads();  // tile clean again; s_next visible
 }
 
+// A batch record's Loop values for the tiled point loops.
+__device__ __forceinline__ Loop tiled_loop(const LiveBatch& rec, uint32_t W, uint32_t H, uint64_t* vb) {
+  Loop L;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) L.P[r][j] = rec.P[r][j];
+    L.t[r] = rec.t[r];
+  }
+  L.W = W;
+  L.H = H;
+  L.vb = vb;
+  const uint32_t rwh = uni(rec.rect_wh), rxy = uni(rec.rect_xy);
+  L.tw = rwh & 0xFFFFu;
+  L.th = rwh >> 16;
+  L.tw8 = L.tw * 8u;
+  L.base8 = 0;
+  L.cx = in_vgpr(uni(0x4B000000u + (rxy & 0xFFFFu)));
+  L.cy = in_vgpr(uni(0x4B000000u + (rxy >> 16)));
+  return L;
+}
+
+// Whether a view's record of a batch can share a two-view pass: 10 bits,
+// tiled, not banded, INSIDE or PARTIAL.
+__device__ __forceinline__ bool pairable(const LiveBatch& rec) {
+  const uint32_t m = rec.mode;
+  return (m & 0xFFu) == 10u && ((m >> 16) & 3u) == 1u && ((m >> 8) & 0xFFu) != (uint32_t)CLS_SLOW;
+}
+__device__ __forceinline__ uint32_t rect_area(const LiveBatch& rec) {
+  return (rec.rect_wh & 0xFFFFu) * (rec.rect_wh >> 16);
+}
+
+// Groups in flight per wave in a two-view pass: each group carries twice the
+// work of a one-view group, so fewer cover the same memory latency.
+constexpr int PAIR_PF = PREFETCH < 3 ? PREFETCH : 3;
+
+// One batch into two views in one pass over its points: view A's sub-tile
+// first in the LDS tile, view B's right after it (the two rectangles fit the
+// tile together), one barrier after the points, both flushes, one barrier.
+__device__ __forceinline__ void render_pair(const LiveBatch& ra, const ViewOut& va, const LiveBatch& rb,
+                                            const ViewOut& vb, const Streams& st, uint64_t* tile, uint32_t tid,
+                                            uint32_t wave, uint32_t lane, bool publish, uint32_t next,
+                                            uint32_t* s_next, uint32_t& natom) {
+  const Loop A = tiled_loop(ra, va.W, va.H, va.vb);
+  Loop B = tiled_loop(rb, vb.W, vb.H, vb.vb);
+  const uint32_t na = uni(rect_area(ra));
+  B.base8 = na * 8u;
+  // uniform by construction (one record per workgroup); said so for the compiler
+  const uint32_t first = uni(ra.first), count = uni(ra.count);
+  const int ca = (int)((uni(ra.mode) >> 8) & 0xFFu), cb = (int)((uni(rb.mode) >> 8) & 0xFFu);
+  for (uint32_t c0 = 0; c0 < count; c0 += CHUNK_POINTS) {
+    const uint32_t n = count - c0 < CHUNK_POINTS ? count - c0 : CHUNK_POINTS;
+    if (ca == CLS_INSIDE && cb == CLS_INSIDE)
+      stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+        four_points_pair<CLS_INSIDE, CLS_INSIDE>(A, B, tile, w, i0, nv);
+      });
+    else if (ca == CLS_INSIDE)
+      stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+        four_points_pair<CLS_INSIDE, CLS_PARTIAL>(A, B, tile, w, i0, nv);
+      });
+    else if (cb == CLS_INSIDE)
+      stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+        four_points_pair<CLS_PARTIAL, CLS_INSIDE>(A, B, tile, w, i0, nv);
+      });
+    else
+      stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+        four_points_pair<CLS_PARTIAL, CLS_PARTIAL>(A, B, tile, w, i0, nv);
+      });
+  }
+  __syncthreads();  // both views' points are in their sub-tiles; s_next has been read
+  if (publish && tid == 0) *s_next = next;
+  flush_tile(tile, tid, va.vb, va.W, ra.rect_xy & 0xFFFFu, ra.rect_xy >> 16, A.tw, A.th, natom);
+  flush_tile(tile + na, tid, vb.vb, vb.W, rb.rect_xy & 0xFFFFu, rb.rect_xy >> 16, B.tw, B.th, natom);
+  __syncthreads();  // tile clean again; s_next visible
+}
+
 // The live list (or run list) of nb slots holds nt tiled entries from the
 // front and nd entries with untiled batches from the back (slots nb - 1,
 // nb - 2, ...).  Queue position p of n = nt + nd takes an untiled one iff
@@ -587,12 +733,25 @@ __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4)
     const Run run = a.runs[i];
     uint64_t mask = run.mask;
     bool publish = true;
+    const LiveBatch* const recs = a.sub + (uint64_t)run.batch * a.nviews;
     while (mask) {
       const uint32_t v = run.view0 + (uint32_t)(__ffsll((unsigned long long)mask) - 1);
       mask &= mask - 1;
+      const LiveBatch& rec = recs[v];
+      // the next live view shares the pass when both records allow it and
+      // their rectangles fit the tile together
+      if (mask && pairable(rec)) {
+        const uint32_t v2 = run.view0 + (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+        const LiveBatch& rec2 = recs[v2];
+        if (pairable(rec2) && rect_area(rec) + rect_area(rec2) <= TILE_MAX) {
+          mask &= mask - 1;
+          render_pair(rec, a.v[v], rec2, a.v[v2], st, tile, tid, wave, lane, publish, grab, &s_next, natom);
+          publish = false;
+          continue;
+        }
+      }
       const ViewOut& vo = a.v[v];
-      render_batch(a.sub[(uint64_t)run.batch * a.nviews + v], vo.W, vo.H, vo.vb, st, tile, tid, wave, lane, publish,
-                   grab, &s_next, natom);
+      render_batch(rec, vo.W, vo.H, vo.vb, st, tile, tid, wave, lane, publish, grab, &s_next, natom);
       publish = false;
     }
     i = uni(s_next);

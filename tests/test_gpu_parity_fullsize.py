@@ -138,21 +138,25 @@ def test_c2_force30_frames(ctx, c2):
         _check_eye(ctx, c2.cloud["handle"], c2.B, c2.B.colors, cam, c2.nb, f"C2 orbit {f} FORCE30", precision=30)
 
 
-@pytest.fixture(scope="module")
-def c2_generation(ctx):
-    """The same 1e8 points batched in their generation order (no Morton sort), as bench.py's c2 leg builds them."""
+@pytest.fixture(scope="module", params=[1, 0], ids=["generation", "index"])
+def c2_generation(ctx, request):
+    """The 1e8 points batched without a Morton sort, as bench.py's c2 leg builds them: in the generator's tile
+    order (10 m tiles in serpentine strips) and in its index order (spatially incoherent)."""
     import torch
     import bench
 
-    wl = dict(bench.workload("c2", None), morton=False, name="terrain_1e8_generation")
-    seen = {}
+    wl = dict(bench.workload("c2", None), morton=False, order=request.param, name=f"terrain_1e8_order{request.param}")
+    n = wl["n"]
+    xyz_all, rgba_all = np.empty((n, 3), np.float32), np.empty(n, np.uint32)
 
-    def keep(lo, hi, xyz, rgba):
-        seen["xyz"], seen["rgba"] = xyz, rgba
+    def keep(lo, hi, xyz, rgba):  # the loader reuses its chunk buffers: copy
+        xyz_all[lo:hi] = xyz
+        rgba_all[lo:hi] = rgba
 
-    say("C2 generation order: build on the GPU")
+    say(f"C2 generator order {request.param}, no Morton sort: build on the GPU")
     cloud = bench.load_cloud(ctx, wl, on_chunk=keep)
-    B = oracle.build_cloud(seen["xyz"], seen["rgba"], S, morton=False)
+    B = oracle.build_cloud(xyz_all, rgba_all, S, morton=False)
+    del xyz_all, rgba_all
     yield types.SimpleNamespace(wl=wl, cloud=cloud, B=B, n=wl["n"], nb=cloud["nb"])
     import paper_2204_01287_amd as pr
 
@@ -170,7 +174,8 @@ def test_c2_generation_order(ctx, c2_generation):
         assert np.array_equal(_u32(getattr(v, f)), getattr(g.B, f)), f"{f} differs"
     assert np.array_equal(v.batches.cpu().numpy(), g.B.batches.view(np.uint8)), "batch records differ"
     for f in (0, 45):
-        _check_eye(ctx, g.cloud["handle"], g.B, g.B.colors, synth.orbit_camera(f), g.nb, f"C2 generation order {f}")
+        _check_eye(ctx, g.cloud["handle"], g.B, g.B.colors, synth.orbit_camera(f), g.nb,
+                   f"C2 order {g.wl['order']} frame {f}")
 
 
 # =================================================================== C3: 2e9
