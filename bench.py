@@ -822,6 +822,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--preheat-s", type=float, default=0.3,
+                    help="seconds of untimed frames before the warmup steps (GPU clocks reach their steady state)")
     ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c3")
     ap.add_argument("--n", type=int, default=None, help="override the point count (smaller test runs)")
     ap.add_argument("--cpu-sample", type=int, default=32_000_000)
@@ -900,6 +902,16 @@ def main():
             if e:
                 e[2].record(stream)
 
+    # The clocks of an idle GPU ramp up over the first tens of milliseconds of work: untimed frames until
+    # preheat_s has passed, then the warmup steps, then the timed steps.
+    preheat_frames = 0
+    t_pre = time.perf_counter()
+    while time.perf_counter() - t_pre < args.preheat_s:
+        for _ in range(10):
+            frame()
+        torch.cuda.synchronize()
+        preheat_frames += 10
+    log(f"preheat: {preheat_frames} untimed frames in {time.perf_counter() - t_pre:.3f} s")
     for _ in range(args.warmup):
         frame()
     torch.cuda.synchronize()
@@ -940,6 +952,7 @@ def main():
         "frame_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
         "frame_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
         "wall_s_timed": round(wall, 4),
+        "preheat": {"seconds": args.preheat_s, "frames": preheat_frames},
         "level_points": [sum(s["level_points"][i] for s in per_view) for i in range(3)],
         "culled_batches": [s["culled"] for s in per_view],
         "atomics": [s["atomics"] for s in per_view],

@@ -326,6 +326,68 @@ __device__ __forceinline__ void four_points_pair(const Loop& A, const Loop& B, u
                              __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Two views whose y and w projection rows are bit-equal (a stereo pair whose
+// eyes differ by a shift along the camera's x axis): the y and w chains, the
+// reciprocal, the y floor and the key are computed once; only the x chain and
+// x floor are per view.  Every value equals what four_points_pair computes.
+template <int CA, int CB>
+__device__ __forceinline__ void four_points_pair_shared(const Loop& A, const Loop& B, uint64_t* tile, const Words& w,
+                                                        uint32_t i0, uint32_t nvalid) {
+  const uint32_t Lw[4] = {w.l.x, w.l.y, w.l.z, w.l.w};
+  uint8_t* const tb = reinterpret_cast<uint8_t*>(tile);
+  uint32_t ad[8];
+  uint64_t key[4], old[8];
+  bool ok[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float X, Y, Z;
+    decode<10>(Lw[j], 0u, 0u, X, Y, Z);
+    const Proj pa = project(A, X, Y, Z);
+    Proj pb = pa;
+    pb.hx = __builtin_fmaf(B.P[0][2], Z, __builtin_fmaf(B.P[0][1], Y, __builtin_fmaf(B.P[0][0], X, B.t[0])));
+    ok[j] = (uint32_t)j < nvalid;
+    ok[4 + j] = ok[j];
+    if constexpr (CA != CLS_INSIDE) ok[j] = ok[j] && visible(A, pa);
+    if constexpr (CB != CLS_INSIDE) ok[4 + j] = ok[4 + j] && visible(B, pb);
+    const float r = __builtin_amdgcn_rcpf(pa.hw);
+    const float ty = __builtin_fmaf(pa.hy, r, 0x1p23f);
+    const float ey = __builtin_fmaf(-(ty - 0x1p23f), pa.hw, pa.hy);
+    const float txa = __builtin_fmaf(pa.hx, r, 0x1p23f);
+    const float exa = __builtin_fmaf(-(txa - 0x1p23f), pa.hw, pa.hx);
+    const float txb = __builtin_fmaf(pb.hx, r, 0x1p23f);
+    const float exb = __builtin_fmaf(-(txb - 0x1p23f), pa.hw, pb.hx);
+    const unsigned int by = (unsigned int)(ey < 0.0f);
+    unsigned int bo;
+    const uint32_t lxa = __builtin_subc(__float_as_uint(txa), A.cx, (unsigned int)(exa < 0.0f), &bo);
+    const uint32_t lya = __builtin_subc(__float_as_uint(ty), A.cy, by, &bo);
+    const uint32_t lxb = __builtin_subc(__float_as_uint(txb), B.cx, (unsigned int)(exb < 0.0f), &bo);
+    const uint32_t lyb = __builtin_subc(__float_as_uint(ty), B.cy, by, &bo);
+    key[j] = make_key(pa.hw, i0 + j);
+    ad[j] = __umul24(lya, A.tw8) + (lxa << 3);
+    asm volatile("" : "+v"(ad[j]));
+    ad[4 + j] = __umul24(lyb, B.tw8) + ((lxb << 3) + B.base8);
+    asm volatile("" : "+v"(ad[4 + j]));
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const bool inside = j < 4 ? CA == CLS_INSIDE : CB == CLS_INSIDE;
+    if (inside) {
+      old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      old[j] = 0;
+      if (ok[j])
+        old[j] = __hip_atomic_load(reinterpret_cast<uint64_t*>(tb + ad[j]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (ok[j] && key[j & 3] < old[j])
+      __hip_atomic_fetch_min(reinterpret_cast<uint64_t*>(tb + ad[j]), key[j & 3], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // The coordinate streams of the cloud (low, medium, high words).
 struct Streams {
   const uint32_t* low;
@@ -626,9 +688,34 @@ __device__ __forceinline__ void render_pair(const LiveBatch& ra, const ViewOut& 
   // uniform by construction (one record per workgroup); said so for the compiler
   const uint32_t first = uni(ra.first), count = uni(ra.count);
   const int ca = (int)((uni(ra.mode) >> 8) & 0xFFu), cb = (int)((uni(rb.mode) >> 8) & 0xFFu);
+  // y and w rows bit-equal in both records: shared chains
+  bool shared = true;
+#pragma unroll
+  for (int r = 1; r < 3; ++r) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) shared = shared && __float_as_uint(A.P[r][j]) == __float_as_uint(B.P[r][j]);
+    shared = shared && __float_as_uint(A.t[r]) == __float_as_uint(B.t[r]);
+  }
   for (uint32_t c0 = 0; c0 < count; c0 += CHUNK_POINTS) {
     const uint32_t n = count - c0 < CHUNK_POINTS ? count - c0 : CHUNK_POINTS;
-    if (ca == CLS_INSIDE && cb == CLS_INSIDE)
+    if (shared) {
+      if (ca == CLS_INSIDE && cb == CLS_INSIDE)
+        stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+          four_points_pair_shared<CLS_INSIDE, CLS_INSIDE>(A, B, tile, w, i0, nv);
+        });
+      else if (ca == CLS_INSIDE)
+        stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+          four_points_pair_shared<CLS_INSIDE, CLS_PARTIAL>(A, B, tile, w, i0, nv);
+        });
+      else if (cb == CLS_INSIDE)
+        stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+          four_points_pair_shared<CLS_PARTIAL, CLS_INSIDE>(A, B, tile, w, i0, nv);
+        });
+      else
+        stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
+          four_points_pair_shared<CLS_PARTIAL, CLS_PARTIAL>(A, B, tile, w, i0, nv);
+        });
+    } else if (ca == CLS_INSIDE && cb == CLS_INSIDE)
       stream_chunk<10, false, PAIR_PF>(st, first + c0, n, wave, lane, [&](const Words& w, uint32_t i0, uint32_t nv) {
         four_points_pair<CLS_INSIDE, CLS_INSIDE>(A, B, tile, w, i0, nv);
       });

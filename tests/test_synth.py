@@ -99,3 +99,16 @@ def test_lpc_layout_properties():
     assert np.all(np.diff(nodes[:, 4]) >= 0) and nodes[0, 4] == 0
     pts = np.bincount(nodes[:, 4].astype(int), weights=count)
     assert np.all(pts[1:-1] / pts[:-2] > 3.0) and np.all(pts[1:-1] / pts[:-2] < 5.0)  # about 4x per level
+
+
+def test_stereo_eyes_share_the_y_and_w_rows():
+    """The stereo pairs' eyes differ by a shift along the camera's x axis, so the pixel-space y and w rows of their
+    frame matrices (and of every batch's folded matrix) are bit-equal: the two-view pass of the renderer then
+    computes those chains once.  The x rows differ."""
+    import oracle
+
+    for seed, w, h in ((synth.C3_SEED, 2016, 2240), (synth.C2_SEED, 504, 560)):
+        a, b = synth.stereo_cameras(seed, w, h)
+        pa, pb = oracle.frame_matrix(a.view, a.proj, w, h), oracle.frame_matrix(b.view, b.proj, w, h)
+        assert pa[1:].tobytes() == pb[1:].tobytes()
+        assert not np.array_equal(pa[0], pb[0])
