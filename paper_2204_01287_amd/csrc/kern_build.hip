@@ -215,6 +215,17 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint64_t* __restric
   run[tid] = 0;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  // the whole tile's loads are issued before the ranking starts, so that the
+  // chunks' barriers do not each wait for a memory round trip
+  uint64_t keys[RS_CHUNKS];
+  uint32_t vals[RS_CHUNKS];
+#pragma unroll
+  for (int it = 0; it < RS_CHUNKS; ++it) {
+    const uint64_t i = base + (uint64_t)it * RS_THREADS + tid;
+    keys[it] = i < n ? kin[i] : 0ull;
+    vals[it] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
   for (int it = 0; it < RS_CHUNKS; ++it) {
     wcnt[0][tid] = 0;
     wcnt[1][tid] = 0;
@@ -223,8 +234,8 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint64_t* __restric
     __syncthreads();
     const uint64_t i = base + (uint64_t)it * RS_THREADS + tid;
     const bool valid = i < n;
-    const uint64_t key = valid ? kin[i] : 0ull;
-    const uint32_t val = valid ? vin[i] : 0u;
+    const uint64_t key = keys[it];
+    const uint32_t val = vals[it];
     const uint32_t d = (uint32_t)(key >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -261,13 +272,36 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint64_t* __restric
 }
 
 // ----------------------------------------------------------------- gather
+// Four consecutive outputs per thread: one 16-byte load of their sources, the
+// eight random reads in flight together, 48 + 16 contiguous bytes written.
+// The outputs past the last multiple of four go one per thread.
 __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ xyz, const uint32_t* __restrict__ rgba,
                                                 const uint32_t* __restrict__ perm, uint64_t n,
                                                 float* __restrict__ xyz_out, uint32_t* __restrict__ colors) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const uint64_t n4 = n / 4;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n4; g += stride) {
+    const uint4 p = reinterpret_cast<const uint4*>(perm)[g];
+    uint64_t s[4] = {p.x, p.y, p.z, p.w};
+    float v[12];
+    uint32_t c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (s[j] >= n) s[j] = 4 * g + j;  // a permutation never triggers this; it keeps reads in bounds
+      v[3 * j] = xyz[3 * s[j]];
+      v[3 * j + 1] = xyz[3 * s[j] + 1];
+      v[3 * j + 2] = xyz[3 * s[j] + 2];
+      c[j] = rgba[s[j]];
+    }
+    float4* const xo = reinterpret_cast<float4*>(xyz_out + 12 * g);
+    xo[0] = make_float4(v[0], v[1], v[2], v[3]);
+    xo[1] = make_float4(v[4], v[5], v[6], v[7]);
+    xo[2] = make_float4(v[8], v[9], v[10], v[11]);
+    reinterpret_cast<uint4*>(colors)[g] = make_uint4(c[0], c[1], c[2], c[3]);
+  }
+  for (uint64_t i = 4 * n4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     uint64_t s = perm[i];
-    if (s >= n) s = i;  // a permutation never triggers this; it keeps reads in bounds
+    if (s >= n) s = i;
     xyz_out[3 * i] = xyz[3 * s];
     xyz_out[3 * i + 1] = xyz[3 * s + 1];
     xyz_out[3 * i + 2] = xyz[3 * s + 2];
