@@ -200,7 +200,6 @@ struct SortScratch {
   uint32_t* vals1;  // vals0 is the caller's perm buffer
   uint32_t* hist;   // 256 * nblk
   uint32_t* part;   // scan partial sums
-  float* xyz_sorted;
   uint32_t* aabb;   // 6 ordered keys: min x,y,z then max x,y,z
   uint64_t nblk, npart;
 };
@@ -210,11 +209,15 @@ uint64_t small_scratch_bytes();
 
 hipError_t launch_finite_check(const float* xyz, uint64_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_iota(uint32_t* p, uint64_t n, hipStream_t s);
+// cloud box (with the finite check: flag) and Morton codes
 hipError_t launch_morton_codes(const float* xyz, uint64_t n, uint32_t* aabb, uint64_t* keys, uint32_t* vals,
-                               hipStream_t s);
+                               uint32_t* flag, hipStream_t s);
 hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, hipStream_t s);
-hipError_t launch_gather(const float* xyz, const uint32_t* rgba, const uint32_t* perm, uint64_t n, float* xyz_out,
-                         uint32_t* colors, hipStream_t s);
+// positions and colours in sorted order (perm[sorted] = original), through
+// 16-byte records in the key buffers (xyz_out may be xyz: the gather reads
+// the records)
+hipError_t launch_gather(const SortScratch& sc, const float* xyz, const uint32_t* rgba, const uint32_t* perm,
+                         uint64_t n, float* xyz_out, uint32_t* colors, hipStream_t s);
 hipError_t launch_batch_bbox(const float* xyz, uint64_t n, uint32_t S, uint64_t nb, BatchRec* out, hipStream_t s);
 // variable-size batches: recs[b].first / .count are set, the boxes are filled in
 hipError_t launch_batch_bbox_spans(const float* xyz, uint64_t nb, BatchRec* recs, hipStream_t s);

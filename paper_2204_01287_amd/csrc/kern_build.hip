@@ -1,6 +1,7 @@
 // Load-time build kernels for gfx950 (Sec. 3.1 data structure, Sec. 3.3 Eq. 1).
 //
-//  finite check -> [cloud box -> 63-bit Morton codes -> stable LSD radix sort
+//  finite check (with the Morton order: on the cloud box's loads) -> [cloud
+//  box -> 63-bit Morton codes -> stable LSD radix sort
 //  (8 passes of 8 bits) -> gather] -> per-batch boxes -> Eq. 1 quantise and
 //  split into low / med / high words.
 //
@@ -40,17 +41,24 @@ __global__ void k_aabb_init(uint32_t* aabb) {
   if (threadIdx.x < 6) aabb[threadIdx.x] = threadIdx.x < 3 ? 0xFFFFFFFFu : 0u;
 }
 
-__global__ void __launch_bounds__(256) k_aabb(const float* __restrict__ xyz, uint64_t n, uint32_t* __restrict__ aabb) {
+// The cloud box, and the finite check on the same loads (flag: set if a
+// coordinate is NaN or Inf).
+__global__ void __launch_bounds__(256) k_aabb(const float* __restrict__ xyz, uint64_t n, uint32_t* __restrict__ aabb,
+                                              uint32_t* __restrict__ flag) {
   uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0, 0, 0};
+  bool bad = false;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const uint32_t k = okey(xyz[3 * i + a]);
+      const float f = xyz[3 * i + a];
+      bad |= (__float_as_uint(f) & 0x7F800000u) == 0x7F800000u;
+      const uint32_t k = okey(f);
       mn[a] = min(mn[a], k);
       mx[a] = max(mx[a], k);
     }
   }
+  if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     for (int o = 32; o > 0; o >>= 1) {
@@ -272,40 +280,48 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint64_t* __restric
 }
 
 // ----------------------------------------------------------------- gather
+// Positions and colours of the input as one 16-byte record per point, in
+// input order: the gather then reads one record (one cache line) per output
+// instead of a position and a colour from two arrays.
+__global__ void __launch_bounds__(256) k_interleave(const float* __restrict__ xyz, const uint32_t* __restrict__ rgba,
+                                                    uint64_t n, uint4* __restrict__ rec) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    rec[i] = make_uint4(__float_as_uint(xyz[3 * i]), __float_as_uint(xyz[3 * i + 1]), __float_as_uint(xyz[3 * i + 2]),
+                        rgba[i]);
+}
+
 // Four consecutive outputs per thread: one 16-byte load of their sources, the
-// eight random reads in flight together, 48 + 16 contiguous bytes written.
+// four record reads in flight together, 48 + 16 contiguous bytes written.
 // The outputs past the last multiple of four go one per thread.
-__global__ void __launch_bounds__(256) k_gather(const float* __restrict__ xyz, const uint32_t* __restrict__ rgba,
-                                                const uint32_t* __restrict__ perm, uint64_t n,
-                                                float* __restrict__ xyz_out, uint32_t* __restrict__ colors) {
+__global__ void __launch_bounds__(256) k_gather(const uint4* __restrict__ rec, const uint32_t* __restrict__ perm,
+                                                uint64_t n, float* __restrict__ xyz_out,
+                                                uint32_t* __restrict__ colors) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t n4 = n / 4;
   for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n4; g += stride) {
     const uint4 p = reinterpret_cast<const uint4*>(perm)[g];
     uint64_t s[4] = {p.x, p.y, p.z, p.w};
-    float v[12];
-    uint32_t c[4];
+    uint4 r[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (s[j] >= n) s[j] = 4 * g + j;  // a permutation never triggers this; it keeps reads in bounds
-      v[3 * j] = xyz[3 * s[j]];
-      v[3 * j + 1] = xyz[3 * s[j] + 1];
-      v[3 * j + 2] = xyz[3 * s[j] + 2];
-      c[j] = rgba[s[j]];
+      r[j] = rec[s[j]];
     }
     float4* const xo = reinterpret_cast<float4*>(xyz_out + 12 * g);
-    xo[0] = make_float4(v[0], v[1], v[2], v[3]);
-    xo[1] = make_float4(v[4], v[5], v[6], v[7]);
-    xo[2] = make_float4(v[8], v[9], v[10], v[11]);
-    reinterpret_cast<uint4*>(colors)[g] = make_uint4(c[0], c[1], c[2], c[3]);
+    xo[0] = make_float4(__uint_as_float(r[0].x), __uint_as_float(r[0].y), __uint_as_float(r[0].z), __uint_as_float(r[1].x));
+    xo[1] = make_float4(__uint_as_float(r[1].y), __uint_as_float(r[1].z), __uint_as_float(r[2].x), __uint_as_float(r[2].y));
+    xo[2] = make_float4(__uint_as_float(r[2].z), __uint_as_float(r[3].x), __uint_as_float(r[3].y), __uint_as_float(r[3].z));
+    reinterpret_cast<uint4*>(colors)[g] = make_uint4(r[0].w, r[1].w, r[2].w, r[3].w);
   }
   for (uint64_t i = 4 * n4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     uint64_t s = perm[i];
     if (s >= n) s = i;
-    xyz_out[3 * i] = xyz[3 * s];
-    xyz_out[3 * i + 1] = xyz[3 * s + 1];
-    xyz_out[3 * i + 2] = xyz[3 * s + 2];
-    colors[i] = rgba[s];
+    const uint4 r = rec[s];
+    xyz_out[3 * i] = __uint_as_float(r.x);
+    xyz_out[3 * i + 1] = __uint_as_float(r.y);
+    xyz_out[3 * i + 2] = __uint_as_float(r.z);
+    colors[i] = r.w;
   }
 }
 
@@ -440,7 +456,6 @@ uint64_t sort_scratch_layout(uint64_t n, uint8_t* base, SortScratch* out) {
   s.keys0 = reinterpret_cast<uint64_t*>(take(8 * n));
   s.keys1 = reinterpret_cast<uint64_t*>(take(8 * n));
   s.vals1 = reinterpret_cast<uint32_t*>(take(4 * n));
-  s.xyz_sorted = reinterpret_cast<float*>(take(12 * n));
   s.hist = reinterpret_cast<uint32_t*>(take(4 * m));
   s.part = reinterpret_cast<uint32_t*>(take(4 * s.npart));
   if (out) *out = s;
@@ -459,9 +474,9 @@ hipError_t launch_iota(uint32_t* p, uint64_t n, hipStream_t s) {
 }
 
 hipError_t launch_morton_codes(const float* xyz, uint64_t n, uint32_t* aabb, uint64_t* keys, uint32_t* vals,
-                               hipStream_t s) {
+                               uint32_t* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_aabb_init, dim3(1), dim3(64), 0, s, aabb);
-  hipLaunchKernelGGL(k_aabb, dim3(grid_for(n, 256 * 8, 4096)), dim3(256), 0, s, xyz, n, aabb);
+  hipLaunchKernelGGL(k_aabb, dim3(grid_for(n, 256 * 8, 4096)), dim3(256), 0, s, xyz, n, aabb, flag);
   hipLaunchKernelGGL(k_morton, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, xyz, n, aabb, keys, vals);
   return hipGetLastError();
 }
@@ -494,9 +509,14 @@ hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, 
   return hipSuccess;
 }
 
-hipError_t launch_gather(const float* xyz, const uint32_t* rgba, const uint32_t* perm, uint64_t n, float* xyz_out,
-                         uint32_t* colors, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, xyz, rgba, perm, n, xyz_out, colors);
+hipError_t launch_gather(const SortScratch& sc, const float* xyz, const uint32_t* rgba, const uint32_t* perm,
+                         uint64_t n, float* xyz_out, uint32_t* colors, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  // the records take the two key buffers, free once the sort is done (keys0 then keys1: 16 n bytes)
+  uint4* const rec = reinterpret_cast<uint4*>(sc.keys0);
+  if (reinterpret_cast<uint8_t*>(sc.keys1) + 8 * n < reinterpret_cast<uint8_t*>(rec) + 16 * n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_interleave, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, xyz, rgba, n, rec);
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, rec, perm, n, xyz_out, colors);
   return hipGetLastError();
 }
 

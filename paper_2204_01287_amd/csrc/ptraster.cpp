@@ -362,30 +362,24 @@ pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, in
     const uint32_t* rgba = static_cast<const uint32_t*>(B.rgba);
     uint32_t* perm = static_cast<uint32_t*>(B.perm);
     uint32_t* colors = static_cast<uint32_t*>(B.colors);
-    HIP_TRY(ptr::launch_finite_check(xyz, n, flag, st), "finite check");
-    const float* xyz_render = xyz;
     if (morton) {
       ptr::SortScratch sc;
       uint8_t* base = static_cast<uint8_t*>(B.scratch) + ptr::small_scratch_bytes();
       ptr::sort_scratch_layout(n, base, &sc);
-      HIP_TRY(ptr::launch_morton_codes(xyz, n, sc.aabb, sc.keys0, perm, st), "morton codes");
+      HIP_TRY(ptr::launch_morton_codes(xyz, n, sc.aabb, sc.keys0, perm, flag, st), "morton codes");
       HIP_TRY(ptr::radix_sort_pairs(sc, perm, n, st), "radix sort");
-      HIP_TRY(ptr::launch_gather(xyz, rgba, perm, n, sc.xyz_sorted, colors, st), "gather");
-      xyz_render = sc.xyz_sorted;
+      // sorted positions straight into the caller's xyz buffer (the gather reads copies of the inputs)
+      HIP_TRY(ptr::launch_gather(sc, xyz, rgba, perm, n, static_cast<float*>(B.xyz), colors, st), "gather");
     } else {
+      HIP_TRY(ptr::launch_finite_check(xyz, n, flag, st), "finite check");
       HIP_TRY(ptr::launch_iota(perm, n, st), "iota");
       HIP_TRY(hipMemcpyAsync(colors, rgba, 4 * n, hipMemcpyDeviceToDevice, st), "copy colours");
     }
     ptr::BatchRec* batches = static_cast<ptr::BatchRec*>(B.batches);
-    HIP_TRY(ptr::launch_batch_bbox(xyz_render, n, batch_size, nb, batches, st), "batch boxes");
-    HIP_TRY(ptr::launch_quantize(xyz_render, n, batch_size, batches, static_cast<uint32_t*>(B.low),
+    HIP_TRY(ptr::launch_batch_bbox(xyz, n, batch_size, nb, batches, st), "batch boxes");
+    HIP_TRY(ptr::launch_quantize(xyz, n, batch_size, batches, static_cast<uint32_t*>(B.low),
                                  static_cast<uint32_t*>(B.med), static_cast<uint32_t*>(B.high), st),
             "quantise");
-    if (morton) {  // leave the sorted positions in the caller's xyz buffer
-      ptr::SortScratch sc;
-      ptr::sort_scratch_layout(n, static_cast<uint8_t*>(B.scratch) + ptr::small_scratch_bytes(), &sc);
-      HIP_TRY(hipMemcpyAsync(B.xyz, sc.xyz_sorted, 12 * n, hipMemcpyDeviceToDevice, st), "sorted positions");
-    }
   }
   uint32_t h_flag = 0;
   HIP_TRY(hipMemcpyAsync(&h_flag, flag, sizeof h_flag, hipMemcpyDeviceToHost, st), "read flag");

@@ -226,16 +226,20 @@ def test_maximum_image_size(ctx, c1):
     _check_frame(ctx, dc, B, cam.view, cam.proj, 8192, 8192, "adaptive")
 
 
-def test_non_finite_inputs(ctx):
+@pytest.mark.parametrize("morton", [False, True])
+def test_non_finite_inputs(ctx, morton):
+    """A NaN or infinite coordinate fails the build (with the Morton order the check runs on the cloud box's
+    loads); a bad view matrix or an empty image fails the render."""
     import paper_2204_01287_amd as pr
 
     xyz, rgba = synth.primitives(6, 5000)
-    xyz[4321, 2] = np.nan
-    with pytest.raises(pr.PrError) as e:
-        gpu_build(ctx, xyz, rgba, 64, False)
-    assert e.value.name == "PR_ENONFINITE"
-    xyz[4321, 2] = 1.0
-    dc = gpu_build(ctx, xyz, rgba, 64, False)
+    for bad_value, at in ((np.nan, (4321, 2)), (np.inf, (17, 0)), (-np.inf, (4999, 1))):
+        xyz_bad = xyz.copy()
+        xyz_bad[at] = bad_value
+        with pytest.raises(pr.PrError) as e:
+            gpu_build(ctx, xyz_bad, rgba, 64, morton)
+        assert e.value.name == "PR_ENONFINITE"
+    dc = gpu_build(ctx, xyz, rgba, 64, morton)
     cam = synth.c1_camera()
     bad = cam.view.copy()
     bad[1, 2] = np.inf
