@@ -71,6 +71,8 @@ def _lib_():
         L.or_quantize.argtypes = [P, P, U64, P, P, P]
         L.or_build.argtypes = [P, P, U64, U32, I, P, P, P, P, P, P, P]
         L.or_build.restype = I
+        L.or_spread_multiplier.argtypes = [U64]
+        L.or_spread_multiplier.restype = U64
         L.or_frame_matrix.argtypes = [P, P, U32, U32, P]
         L.or_decide_all.argtypes = [P, P, U64, P, P, U32, U32, ctypes.POINTER(Opts), P]
         L.or_render.argtypes = [P, P, U64, P, U64, P, P, P, P, P, U32, U32, ctypes.POINTER(Opts), P,
@@ -165,7 +167,13 @@ class Built:
         self.nodes = None  # LOD layouts: float64 (nb, 5) = cube origin x, y, z, edge, level
 
 
-def build_cloud(xyz, rgba, S: int = 10240, morton: bool = False) -> Built:
+def spread_multiplier(c: int) -> int:
+    """The step m of the spread order of a c-point batch: position r holds Morton rank (r * m) mod c."""
+    return int(_lib_().or_spread_multiplier(c))
+
+
+def build_cloud(xyz, rgba, S: int = 10240, morton: int = 0) -> Built:
+    """morton: 0 input order, 1 Morton order, 2 Morton order with every batch in the spread order."""
     xyz = _c(xyz, np.float32)
     rgba = _c(rgba, np.uint32)
     n = xyz.shape[0]

@@ -10,7 +10,8 @@
  * What is computed (the reading of the paper is spelled out per function):
  *   O1 validate          -- every coordinate finite, n < 2^32.
  *   O2 Morton order      -- Sec. 3.1 (group consecutive points, optionally
- *                           sorted by Morton code / z-order).
+ *                           sorted by Morton code / z-order); optionally each
+ *                           batch in a spread order (this build's own option).
  *   O3 batches           -- Sec. 3.1 and Fig. "batches memory": fixed-size
  *                           runs of consecutive points plus their bounding box.
  *   O4 quantise + split  -- Sec. 3.3, Eq. 1 and the 10-bit packing listing.
@@ -230,12 +231,34 @@ void or_quantize(const float* xyz, const or_batch* batches, uint64_t nb, uint32_
   }
 }
 
-/* Whole load-time build: optional Morton order, batches, Eq. 1 split.
+/* Spread order inside a batch (this build's own option, not the paper's):
+ * the batch's c points, in Morton order, are stored so that position r
+ * holds Morton rank (r * m) mod c, m the first integer >= max(1,
+ * floor(c * 0.6180339887...)) with gcd(m, c) = 1; floor(c * golden
+ * fraction) is taken as (c * 2654435769) >> 32.  Consecutive positions then
+ * jump across the whole batch, while the batch keeps its points. */
+static uint64_t gcd_u64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+uint64_t or_spread_multiplier(uint64_t c) {
+  uint64_t m = (c * 2654435769ull) >> 32;
+  if (m < 1) m = 1;
+  while (gcd_u64(m, c) != 1) ++m;
+  return m;
+}
+
+/* Whole load-time build: optional Morton order (morton = 1; 2: Morton order
+ * with every batch in the spread order above), batches, Eq. 1 split.
  * Outputs are in render order; perm[render index] = input index. */
 int or_build(const float* xyz, const uint32_t* rgba, uint64_t n, uint32_t S, int morton,
              float* xyz_out, uint32_t* colors, uint32_t* perm, or_batch* batches, uint32_t* low,
              uint32_t* med, uint32_t* high) {
-  if (n >= 0xFFFFFFFFull || S == 0) return -1;
+  if (n >= 0xFFFFFFFFull || S == 0 || morton < 0 || morton > 2) return -1;
   if (or_validate(xyz, n) >= 0) return -5;
   if (morton) {
     float mn[3], mx[3];
@@ -246,6 +269,17 @@ int or_build(const float* xyz, const uint32_t* rgba, uint64_t n, uint32_t S, int
     int rc = or_morton_order(codes, n, perm);
     free(codes);
     if (rc) return rc;
+    if (morton == 2) {
+      uint32_t* sorted = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+      if (!sorted) return -2;
+      memcpy(sorted, perm, sizeof(uint32_t) * n);
+      for (uint64_t b0 = 0; b0 < n; b0 += S) {
+        const uint64_t c = (n - b0 < S) ? n - b0 : S;
+        const uint64_t m = or_spread_multiplier(c);
+        for (uint64_t r = 0; r < c; ++r) perm[b0 + r] = sorted[b0 + (r * m) % c];
+      }
+      free(sorted);
+    }
   } else {
     for (uint64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
   }

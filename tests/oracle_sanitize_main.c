@@ -68,7 +68,7 @@ int main(void) {
   uint32_t* fb = malloc(4ull * w * h);
   or_decision* dec = malloc(sizeof(or_decision) * nb);
   const double eyes[4][3] = {{5, -20, 15}, {5, 5, 5}, {30, 30, 2}, {5, 5, 40}};
-  for (int morton = 0; morton < 2; ++morton) {
+  for (int morton = 0; morton < 3; ++morton) {  // input order, Morton order, Morton + spread order
     if (or_build(xyz, rgba, n, S, morton, xo, col, perm, bat, low, med, high) != 0) return 2;
     for (int c = 0; c < 4; ++c) {
       float view[16], proj[16];

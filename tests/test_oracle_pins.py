@@ -316,6 +316,36 @@ def test_morton_grid_z_curve():
     assert shuffled[order].tolist() == g.tolist()
 
 
+@pytest.mark.parametrize("n,S", [(5003, 64), (10240 * 3 + 777, 10240), (7, 4), (1, 4)])
+def test_spread_order_keeps_each_batch_and_steps_across_it(n, S):
+    """The spread build (morton = 2) stores each batch of the Morton build in another order: the same points, the
+    same batch records, and Eq. 1 words that follow the points; inside a batch of c points the Morton ranks advance
+    by one fixed step coprime with c, about 0.618 c, so that neighbouring positions lie far apart in the batch."""
+    rng = np.random.default_rng(n)
+    xyz = rng.uniform(-20, 20, (n, 3)).astype(np.float32)
+    rgba = rng.integers(0, 2**32, n, dtype=np.uint32)
+    A = oracle.build_cloud(xyz, rgba, S, morton=1)
+    B = oracle.build_cloud(xyz, rgba, S, morton=2)
+    assert np.array_equal(A.batches, B.batches)
+    pos_in_a = np.empty(n, np.int64)
+    pos_in_a[A.perm] = np.arange(n)
+    for b0 in range(0, n, S):
+        c = min(S, n - b0)
+        ranks = pos_in_a[B.perm[b0:b0 + c]] - b0  # Morton rank inside the batch of each spread position
+        assert sorted(ranks.tolist()) == list(range(c))
+        if c > 1:
+            steps = np.unique((ranks[1:] - ranks[:-1]) % c)
+            assert len(steps) == 1 and math.gcd(int(steps[0]), c) == 1
+            assert abs(int(steps[0]) - 0.6180339887 * c) < 8
+        assert ranks[0] == 0
+        src = A.perm[b0 + ranks]
+        assert np.array_equal(B.perm[b0:b0 + c], src)
+        assert np.array_equal(B.xyz[b0:b0 + c], A.xyz[b0 + ranks])
+        assert np.array_equal(B.colors[b0:b0 + c], A.colors[b0 + ranks])
+        for f in ("low", "med", "high"):
+            assert np.array_equal(getattr(B, f)[b0:b0 + c], getattr(A, f)[b0 + ranks])
+
+
 def test_morton_order_is_stable():
     rng = np.random.default_rng(9)
     base = rng.uniform(0, 1, (50, 3)).astype(np.float32)
