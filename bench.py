@@ -353,6 +353,57 @@ def multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, plain
     return res
 
 
+def spread_leg(pr, ctx, cloud, cams, vbs, fbs, frame, processed, steps, warmup):
+    """The headline cloud rebuilt in place in the spread order (PR_ORDER_MORTON_SPREAD: the same batches, each
+    stored with a golden-ratio stride over its Morton ranks): the plain step and the multi-view step again."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    mem, n = cloud["mem"], cloud["n"]
+    # the xyz buffer already holds the Morton order; the colours in that order become the build's input colours
+    mem["rgba"][: 4 * n].copy_(mem["colors"][: 4 * n])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pr.pr_build_batches(ctx.handle, cloud["handle"], 10240, pr.PR_ORDER_MORTON_SPREAD)
+    t_build = time.perf_counter() - t0
+    need = pr.pr_views_work_bytes(cloud["handle"], len(cams))
+    work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    vlist = [(c.view, c.proj, c.width, c.height, vb) for c, vb in zip(cams, vbs)]
+
+    def frame_views():
+        pr.pr_render_views(ctx.handle, cloud["handle"], vlist, None, work, need)
+        for c, vb, fb in zip(cams, vbs, fbs):
+            pr.pr_resolve(ctx.handle, cloud["handle"], vb, c.width, c.height, 0xFF000000, fb)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        pr.pr_sync(ctx.handle)
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    plain = timed(frame)
+    mv = timed(frame_views)
+    rv = timed_ms(lambda: pr.pr_render_views(ctx.handle, cloud["handle"], vlist, None, work, need), steps, warmup)
+    c = cams[0]
+    res_ms = timed_ms(lambda: pr.pr_resolve(ctx.handle, cloud["handle"], vbs[0], c.width, c.height, 0xFF000000,
+                                            fbs[0]), steps, warmup)
+    res = {"build_s": round(t_build, 3),
+           "plain": {"ms_per_step": round(plain, 4), "gpts": round(processed / (plain * 1e-3) / 1e9, 3)},
+           "multiview": {"ms_per_step": round(mv, 4), "gpts": round(processed / (mv * 1e-3) / 1e9, 3),
+                         "render_views_ms": round(rv, 4)},
+           "resolve_ms": round(res_ms, 4)}
+    log(f"spread order: {res}")
+    return res
+
+
 def hqs_leg(pr, ctx, cloud, cams, processed, steps, warmup, window=1.01):
     """The stereo step with high-quality shading (Sec. 3.6) instead of the plain resolve: per eye, the render,
     the shading pass (colour sums within the depth window) and the averaging resolve."""
@@ -682,15 +733,16 @@ def c2_leg(pr, ctx, steps: int, warmup: int, n: int = 100_000_000):
     t0 = time.perf_counter()
     # generation order: 10 m tiles in serpentine strips (aerial-strip-like, already compact batches); index order:
     # the generator's points by index, spatially incoherent (like the paper's scan order of laser scans)
-    for order, morton, gen in (("morton", True, 1), ("generation", False, 1), ("index", False, 0)):
+    for order, morton, gen in (("morton", 1, 1), ("morton_spread", 2, 1), ("generation", 0, 1), ("index", 0, 0)):
         clouds[order] = load_cloud(ctx, dict(name=f"terrain_1e8_{order}", seed=synth.C2_SEED, n=n, morton=morton,
                                              order=gen))
-    log(f"c2: three 1e8-point builds in {time.perf_counter() - t0:.1f} s")
+    log(f"c2: four 1e8-point builds in {time.perf_counter() - t0:.1f} s")
     w, h = cams[0].width, cams[0].height
     vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
     fb = torch.empty(w * h, dtype=torch.int32, device="cuda")
     variants = {"morton_adaptive": ("morton", pr.PR_ADAPTIVE, 0),
                 "morton_force30": ("morton", pr.PR_FORCE30, 0),
+                "morton_spread_adaptive": ("morton_spread", pr.PR_ADAPTIVE, 0),
                 "generation_adaptive": ("generation", pr.PR_ADAPTIVE, 0),
                 "index_order_adaptive": ("index", pr.PR_ADAPTIVE, 0),
                 "morton_adaptive_prefetch1": ("morton", pr.PR_ADAPTIVE, d1)}
@@ -734,6 +786,7 @@ def c2_leg(pr, ctx, steps: int, warmup: int, n: int = 100_000_000):
     out["speedup_morton_vs_generation"] = round(out["generation_adaptive"]["ms_per_frame"] / base, 3)
     out["speedup_morton_vs_index_order"] = round(out["index_order_adaptive"]["ms_per_frame"] / base, 3)
     out["speedup_prefetch_vs_depth1"] = round(out["morton_adaptive_prefetch1"]["ms_per_frame"] / base, 3)
+    out["speedup_spread_vs_morton"] = round(base / out["morton_spread_adaptive"]["ms_per_frame"], 3)
     pr.pr_sync(ctx.handle)
     for c in clouds.values():
         pr.pr_cloud_free(c["handle"])
@@ -840,6 +893,8 @@ def main():
     ap.add_argument("--array-points", type=int, default=500_000_000,
                     help="points of the 64-camera array leg with the batch-size autotuner (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner leg on the headline workload")
+    ap.add_argument("--no-spread", action="store_true",
+                    help="skip the headline cloud rebuilt in the spread order (PR_ORDER_MORTON_SPREAD)")
     ap.add_argument("--served-requests", type=int, default=10000)
     ap.add_argument("--served-rates", type=str, default="500,4000",
                     help="offered request rates per second (comma-separated)")
@@ -1002,6 +1057,8 @@ def main():
     out["hqs"] = hqs_leg(pr, ctx, cloud, cams, processed, args.steps, args.warmup)
     if not args.no_autotune:
         out["autotune"] = autotune_leg(pr, ctx, cloud, cams, vbs, frame, ms_per_step, args.steps, args.warmup)
+    if not args.no_spread:
+        out["spread_order"] = spread_leg(pr, ctx, cloud, cams, vbs, fbs, frame, processed, args.steps, args.warmup)
     pr.pr_cloud_free(cloud["handle"])
     cloud["mem"].clear()
     torch.cuda.empty_cache()

@@ -161,13 +161,30 @@ pr_status pr_cloud_sizes_spans(uint64_t n, uint64_t nb, pr_sizes* out);
 pr_status pr_load_points(pr_ctx* ctx, const float* xyz, const uint32_t* rgba, uint64_t n,
                          int src_on_device, const pr_cloud_bufs* bufs, pr_cloud** out);
 
+/* Point orders of pr_build_batches. */
+enum {
+  PR_ORDER_INPUT = 0,          /* the order of the xyz buffer */
+  PR_ORDER_MORTON = 1,         /* stable Morton order (Sec. 3.1) */
+  PR_ORDER_MORTON_SPREAD = 2   /* the batches of PR_ORDER_MORTON, each stored in the spread order below */
+};
+
 /* Load-time build (Sec. 3.1, 3.3): checks every coordinate is finite;
- * optionally sorts the points by 63-bit Morton code (21 bits per axis over the
- * cloud box, x in the lowest bit; stable); groups batch_size consecutive points
- * into batches with their fp32 bounding boxes; quantises every coordinate by
- * Eq. 1 relative to its batch box and splits the 30 bits into low / med /
- * high words.  Synchronises the stream once.  PR_ENONFINITE if any
- * coordinate is NaN or Inf. */
+ * orders the points (morton: one of PR_ORDER_*; nonzero needs the sort
+ * scratch of pr_cloud_sizes): PR_ORDER_MORTON sorts them by 63-bit Morton
+ * code (21 bits per axis over the cloud box, x in the lowest bit; stable);
+ * groups batch_size consecutive points into batches with their fp32 bounding
+ * boxes; quantises every coordinate by Eq. 1 relative to its batch box and
+ * splits the 30 bits into low / med / high words.  PR_ORDER_MORTON_SPREAD
+ * (an option of this library; the paper fixes no order inside a batch) keeps
+ * the same batches but stores a batch of c points so that position r holds
+ * its Morton rank (r * m) mod c, m the first integer >= max(1,
+ * (c * 2654435769) >> 32) (about 0.618 c) coprime with c: a workgroup's
+ * consecutive points then spread over the batch's pixels, which shortens the
+ * queues on shared tile entries when many points fall on few pixels (far
+ * views, two-view passes), at the cost of a less coherent colour gather in
+ * pr_resolve.  perm and colors follow the stored order.  Synchronises the
+ * stream once.  PR_ENONFINITE if any coordinate is NaN or Inf, PR_EINVAL for
+ * an unknown order. */
 pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton);
 
 /* One view of a multi-view render: matrices and image size as for

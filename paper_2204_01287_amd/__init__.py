@@ -11,7 +11,8 @@ Importing fails loudly if the library has not been built
 (``python paper_2204_01287_amd/build.py`` or ``__graft_entry__.build()``).
 """
 from ._binding import (  # noqa: F401
-    PR_ADAPTIVE, PR_EMPTY, PR_FORCE10, PR_FORCE20, PR_FORCE30, PR_MAX_VIEWS, PrError, Sizes, CloudBufs, RenderOpts,
+    PR_ADAPTIVE, PR_EMPTY, PR_FORCE10, PR_FORCE20, PR_FORCE30, PR_MAX_VIEWS, PR_ORDER_INPUT, PR_ORDER_MORTON,
+    PR_ORDER_MORTON_SPREAD, PrError, Sizes, CloudBufs, RenderOpts,
     Stats, View, pr_views_work_bytes, pr_render_views, pr_cloud_drop_load_buffers, pr_render_hqs, pr_cloud_sizes_spans,
     pr_build_batches_spans, LodNode, lod_nodes, BUFFER_FIELDS, RasterShape, Tuning, TuneTrial, pr_raster_shapes,
     pr_set_tuning, pr_get_tuning, pr_autotune, pr_stream_probe, pr_render_views_static, PR_STATIC_WORK_BYTES,

@@ -25,6 +25,7 @@ import torch  # noqa: E402,F401
 lib = ctypes.CDLL(LIB_PATH)
 
 PR_ADAPTIVE, PR_FORCE10, PR_FORCE20, PR_FORCE30 = 0, 10, 20, 30
+PR_ORDER_INPUT, PR_ORDER_MORTON, PR_ORDER_MORTON_SPREAD = 0, 1, 2  # point orders of pr_build_batches
 PR_EMPTY = 0xFFFFFFFFFFFFFFFF
 PR_MAX_VIEWS = 64
 _STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "PR_ESTATE",
@@ -183,7 +184,7 @@ def pr_destroy(ctx):
     lib.pr_destroy(ctx)
 
 
-def pr_cloud_sizes(n: int, batch_size: int, morton: bool) -> Sizes:
+def pr_cloud_sizes(n: int, batch_size: int, morton: int) -> Sizes:
     s = Sizes()
     _check(lib.pr_cloud_sizes(n, batch_size, int(morton), ctypes.byref(s)), "pr_cloud_sizes")
     return s
@@ -196,7 +197,8 @@ def pr_load_points(ctx, xyz, rgba, n: int, src_on_device: bool, bufs: CloudBufs)
     return h.value
 
 
-def pr_build_batches(ctx, cloud, batch_size: int, morton: bool):
+def pr_build_batches(ctx, cloud, batch_size: int, morton: int):
+    """morton: PR_ORDER_INPUT (0 / False), PR_ORDER_MORTON (1 / True) or PR_ORDER_MORTON_SPREAD (2)."""
     _check(lib.pr_build_batches(ctx, cloud, batch_size, int(morton)), "pr_build_batches")
 
 
@@ -371,9 +373,10 @@ class DeviceCloud:
 
     FIELDS = BUFFER_FIELDS
 
-    def __init__(self, ctx: Context, xyz, rgba, batch_size: int = 10240, morton: bool = False, spans=None,
+    def __init__(self, ctx: Context, xyz, rgba, batch_size: int = 10240, morton: int = PR_ORDER_INPUT, spans=None,
                  nodes=None):
-        """Fixed-size batches of batch_size points (optionally Morton-sorted), or, with spans (uint32 (nb, 2) =
+        """Fixed-size batches of batch_size points in one of the PR_ORDER_* orders (False / True for input / Morton
+        order), or, with spans (uint32 (nb, 2) =
         first, count), the variable-size batches of a level-of-detail layout with optional nodes (float64 (nb, 5))."""
         import torch
 

@@ -203,7 +203,7 @@ struct SortScratch {
   uint32_t* aabb;   // 6 ordered keys: min x,y,z then max x,y,z
   uint64_t nblk, npart;
 };
-// Scratch layout for n points (morton = 1); returns total bytes.
+// Scratch layout for n points (a Morton order); returns total bytes.
 uint64_t sort_scratch_layout(uint64_t n, uint8_t* base, SortScratch* out);
 uint64_t small_scratch_bytes();
 
@@ -216,8 +216,14 @@ hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, 
 // positions and colours in sorted order (perm[sorted] = original), through
 // 16-byte records in the key buffers (xyz_out may be xyz: the gather reads
 // the records)
-hipError_t launch_gather(const SortScratch& sc, const float* xyz, const uint32_t* rgba, const uint32_t* perm,
-                         uint64_t n, float* xyz_out, uint32_t* colors, hipStream_t s);
+// spread: every batch of batch_size points (the last one shorter) in the spread
+// order (position r <- Morton rank (r * m) mod c, m = spread_step(c)); perm is
+// then rewritten in that order
+hipError_t launch_gather(const SortScratch& sc, const float* xyz, const uint32_t* rgba, uint32_t* perm,
+                         uint64_t n, uint32_t batch_size, bool spread, float* xyz_out, uint32_t* colors,
+                         hipStream_t s);
+// the first integer >= max(1, floor(c * 0.6180339887...)) coprime with c
+uint64_t spread_step(uint64_t c);
 hipError_t launch_batch_bbox(const float* xyz, uint64_t n, uint32_t S, uint64_t nb, BatchRec* out, hipStream_t s);
 // variable-size batches: recs[b].first / .count are set, the boxes are filled in
 hipError_t launch_batch_bbox_spans(const float* xyz, uint64_t nb, BatchRec* recs, hipStream_t s);

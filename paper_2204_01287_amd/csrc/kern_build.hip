@@ -291,17 +291,48 @@ __global__ void __launch_bounds__(256) k_interleave(const float* __restrict__ xy
                         rgba[i]);
 }
 
+// The batches of a spread build: each batch of c points is stored in the
+// order position r <- Morton rank (r * m) mod c (m: step for a full batch,
+// m_last for the last batch when it is shorter).
+struct Spread {
+  uint64_t S, m, c_last, m_last;
+};
+__device__ __forceinline__ uint64_t spread_source(uint64_t i, const Spread& sp, uint64_t n) {
+  const uint64_t b0 = i - i % sp.S;
+  const bool full = b0 + sp.S <= n;
+  const uint64_t c = full ? sp.S : sp.c_last, m = full ? sp.m : sp.m_last;
+  return b0 + ((i - b0) * m) % c;
+}
+
 // Four consecutive outputs per thread: one 16-byte load of their sources, the
 // four record reads in flight together, 48 + 16 contiguous bytes written.
-// The outputs past the last multiple of four go one per thread.
+// The outputs past the last multiple of four go one per thread.  SPREAD: the
+// sources come from the Morton positions of the spread order (perm_in), and
+// perm_out receives them.
+template <bool SPREAD>
 __global__ void __launch_bounds__(256) k_gather(const uint4* __restrict__ rec, const uint32_t* __restrict__ perm,
-                                                uint64_t n, float* __restrict__ xyz_out,
-                                                uint32_t* __restrict__ colors) {
+                                                uint32_t* __restrict__ perm_out, Spread sp, uint64_t n,
+                                                float* __restrict__ xyz_out, uint32_t* __restrict__ colors) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t n4 = n / 4;
   for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n4; g += stride) {
-    const uint4 p = reinterpret_cast<const uint4*>(perm)[g];
-    uint64_t s[4] = {p.x, p.y, p.z, p.w};
+    uint64_t s[4];
+    if constexpr (SPREAD) {
+      uint32_t q[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint64_t src = spread_source(4 * g + j, sp, n);
+        q[j] = perm[src < n ? src : 4 * g + j];
+        s[j] = q[j];
+      }
+      reinterpret_cast<uint4*>(perm_out)[g] = make_uint4(q[0], q[1], q[2], q[3]);
+    } else {
+      const uint4 p = reinterpret_cast<const uint4*>(perm)[g];
+      s[0] = p.x;
+      s[1] = p.y;
+      s[2] = p.z;
+      s[3] = p.w;
+    }
     uint4 r[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -315,7 +346,14 @@ __global__ void __launch_bounds__(256) k_gather(const uint4* __restrict__ rec, c
     reinterpret_cast<uint4*>(colors)[g] = make_uint4(r[0].w, r[1].w, r[2].w, r[3].w);
   }
   for (uint64_t i = 4 * n4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    uint64_t s = perm[i];
+    uint64_t s;
+    if constexpr (SPREAD) {
+      const uint64_t src = spread_source(i, sp, n);
+      s = perm[src < n ? src : i];
+      perm_out[i] = (uint32_t)s;
+    } else {
+      s = perm[i];
+    }
     if (s >= n) s = i;
     const uint4 r = rec[s];
     xyz_out[3 * i] = __uint_as_float(r.x);
@@ -509,14 +547,43 @@ hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, 
   return hipSuccess;
 }
 
-hipError_t launch_gather(const SortScratch& sc, const float* xyz, const uint32_t* rgba, const uint32_t* perm,
-                         uint64_t n, float* xyz_out, uint32_t* colors, hipStream_t s) {
+uint64_t spread_step(uint64_t c) {
+  uint64_t m = (c * 2654435769ull) >> 32;  // floor(c * golden fraction), in 32-bit fixed point
+  if (m < 1) m = 1;
+  for (;;) {
+    uint64_t a = m, b = c;
+    while (b) {
+      const uint64_t t = a % b;
+      a = b;
+      b = t;
+    }
+    if (a == 1) return m;
+    ++m;
+  }
+}
+
+hipError_t launch_gather(const SortScratch& sc, const float* xyz, const uint32_t* rgba, uint32_t* perm,
+                         uint64_t n, uint32_t batch_size, bool spread, float* xyz_out, uint32_t* colors,
+                         hipStream_t s) {
   if (n == 0) return hipSuccess;
   // the records take the two key buffers, free once the sort is done (keys0 then keys1: 16 n bytes)
   uint4* const rec = reinterpret_cast<uint4*>(sc.keys0);
   if (reinterpret_cast<uint8_t*>(sc.keys1) + 8 * n < reinterpret_cast<uint8_t*>(rec) + 16 * n) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_interleave, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, xyz, rgba, n, rec);
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, rec, perm, n, xyz_out, colors);
+  const dim3 grid(grid_for(n, 256 * 4));
+  if (!spread) {
+    hipLaunchKernelGGL(k_gather<false>, grid, dim3(256), 0, s, rec, perm, perm, Spread{}, n, xyz_out, colors);
+    return hipGetLastError();
+  }
+  // the sorted order moves to the free value buffer; the spread order is written to perm
+  hipError_t e = hipMemcpyAsync(sc.vals1, perm, 4 * n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  Spread sp;
+  sp.S = batch_size;
+  sp.m = spread_step(batch_size);
+  sp.c_last = n % batch_size ? n % batch_size : batch_size;
+  sp.m_last = spread_step(sp.c_last);
+  hipLaunchKernelGGL(k_gather<true>, grid, dim3(256), 0, s, rec, sc.vals1, perm, sp, n, xyz_out, colors);
   return hipGetLastError();
 }
 

@@ -334,6 +334,9 @@ pr_status pr_build_batches_spans(pr_ctx* ctx, pr_cloud* cloud, const uint32_t* s
 
 pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton) {
   if (!ctx || !cloud) return fail(PR_EINVAL, "pr_build_batches: NULL argument");
+  if (morton < PR_ORDER_INPUT || morton > PR_ORDER_MORTON_SPREAD)
+    return fail(PR_EINVAL, "pr_build_batches: order %d is not PR_ORDER_INPUT, PR_ORDER_MORTON or PR_ORDER_MORTON_SPREAD",
+                morton);
   if (cloud->ctx != ctx) return fail(PR_EINVAL, "pr_build_batches: cloud belongs to another context");
   if (cloud->load_dropped) return fail(PR_ESTATE, "pr_build_batches: the cloud's load buffers were released");
   pr_sizes need;
@@ -369,7 +372,9 @@ pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, in
       HIP_TRY(ptr::launch_morton_codes(xyz, n, sc.aabb, sc.keys0, perm, flag, st), "morton codes");
       HIP_TRY(ptr::radix_sort_pairs(sc, perm, n, st), "radix sort");
       // sorted positions straight into the caller's xyz buffer (the gather reads copies of the inputs)
-      HIP_TRY(ptr::launch_gather(sc, xyz, rgba, perm, n, static_cast<float*>(B.xyz), colors, st), "gather");
+      HIP_TRY(ptr::launch_gather(sc, xyz, rgba, perm, n, batch_size, morton == PR_ORDER_MORTON_SPREAD,
+                                 static_cast<float*>(B.xyz), colors, st),
+              "gather");
     } else {
       HIP_TRY(ptr::launch_finite_check(xyz, n, flag, st), "finite check");
       HIP_TRY(ptr::launch_iota(perm, n, st), "iota");
@@ -387,7 +392,7 @@ pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, in
   if (h_flag) return fail(PR_ENONFINITE, "pr_build_batches: a coordinate is NaN or Inf");
   cloud->nb = nb;
   cloud->batch_size = batch_size;
-  cloud->morton = morton ? 1 : 0;
+  cloud->morton = morton;
   cloud->lod = 0;
   cloud->built = 1;
   return PR_OK;

@@ -113,6 +113,15 @@ def test_stereo_pair(ctx, terrain):
     _check(ctx, dc, B, cams)
 
 
+def test_stereo_pair_spread_order(ctx):
+    """The two-view pass over a build in the spread order (PR_ORDER_MORTON_SPREAD), with a third view of another
+    size in the same launch."""
+    xyz, rgba = synth.terrain(synth.C2_SEED, 1_000_000, order=1)
+    dc, B = _cloud(ctx, xyz, rgba, 10240, 2)
+    cams = synth.stereo_cameras(synth.C2_SEED, 504, 560) + [synth.orbit_camera(7, width=640, height=360)]
+    _check(ctx, dc, B, cams)
+
+
 def test_more_views_than_one_classify_launch(ctx, terrain):
     """20 views of mixed sizes: two classify launches, runs of both in one render launch."""
     dc, B = terrain

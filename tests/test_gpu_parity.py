@@ -206,13 +206,43 @@ def test_terrain_stereo_pair(ctx, terrain_small):
         _check_frame(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, "adaptive")
 
 
+@pytest.fixture(scope="module")
+def terrain_spread(ctx):
+    xyz, rgba = synth.terrain(synth.C2_SEED, 2_000_000, order=1)
+    return _both(ctx, xyz, rgba, 10240, 2)
+
+
+def test_terrain_spread_build_and_frames(ctx, terrain_spread):
+    """The spread order (each Morton batch stored with a golden-ratio stride over its ranks): build outputs, orbit
+    frames in both precision modes and the stereo pair equal the oracle's spread build."""
+    dc, B = terrain_spread
+    assert_build_equal(gpu_build_outputs(dc), B)
+    for frame in (0, 29):
+        cam = synth.orbit_camera(frame)
+        _check_frame(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, "adaptive")
+        _check_frame(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, "force30")
+    for cam in synth.stereo_cameras(synth.C2_SEED, 504, 560):
+        _check_frame(ctx, dc, B, cam.view, cam.proj, cam.width, cam.height, "adaptive")
+
+
+def test_unknown_order_is_refused(ctx):
+    import paper_2204_01287_amd as pr
+
+    xyz, rgba = synth.primitives(5, 1000)
+    with pytest.raises(pr.PrError) as e:
+        gpu_build(ctx, xyz, rgba, 64, 3)
+    assert e.value.name == "PR_EINVAL"
+
+
 # ----------------------------------------------------------------- edges
 @pytest.mark.parametrize("n,S", [(0, 64), (1, 4), (5, 4), (10241, 10240), (20480, 10240), (1003, 64), (50003, 1000),
                                  (600001, 262144)])
 def test_ragged_and_empty(ctx, n, S):
     xyz, rgba = synth.primitives(5, max(n, 1))
     xyz, rgba = xyz[:n], rgba[:n]
-    dc, B = _both(ctx, xyz, rgba, S, n % 2 == 1)
+    # odd n: Morton order, and every third case of those in the spread order (ragged last batches included)
+    order = (2 if n % 3 == 2 else 1) if n % 2 == 1 else 0
+    dc, B = _both(ctx, xyz, rgba, S, order)
     if n:
         assert_build_equal(gpu_build_outputs(dc), B)
     cam = synth.c1_camera()
