@@ -173,7 +173,8 @@ def spread_multiplier(c: int) -> int:
 
 
 def build_cloud(xyz, rgba, S: int = 10240, morton: int = 0) -> Built:
-    """morton: 0 input order, 1 Morton order, 2 Morton order with every batch in the spread order."""
+    """morton: 0 input order, 1 Morton order, 2 Morton order with every batch in the spread order (position r holds
+    the batch's Morton rank (r * m) mod c, m = spread_multiplier(c))."""
     xyz = _c(xyz, np.float32)
     rgba = _c(rgba, np.uint32)
     n = xyz.shape[0]

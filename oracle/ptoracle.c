@@ -233,10 +233,11 @@ void or_quantize(const float* xyz, const or_batch* batches, uint64_t nb, uint32_
 
 /* Spread order inside a batch (this build's own option, not the paper's):
  * the batch's c points, in Morton order, are stored so that position r
- * holds Morton rank (r * m) mod c, m the first integer >= max(1,
- * floor(c * 0.6180339887...)) with gcd(m, c) = 1; floor(c * golden
- * fraction) is taken as (c * 2654435769) >> 32.  Consecutive positions then
- * jump across the whole batch, while the batch keeps its points. */
+ * holds Morton rank (r * m) mod c, m the first integer >= floor(c / 4) + 1
+ * with gcd(m, c) = 1.  Position 4q + j then holds rank 4q + j m (mod c):
+ * the j-th points of consecutive quadruples are Morton neighbours in the
+ * j-th quarter of the batch, and the four points of one quadruple lie in
+ * four different quarters.  The batch keeps its points. */
 static uint64_t gcd_u64(uint64_t a, uint64_t b) {
   while (b) {
     uint64_t t = a % b;
@@ -246,8 +247,7 @@ static uint64_t gcd_u64(uint64_t a, uint64_t b) {
   return a;
 }
 uint64_t or_spread_multiplier(uint64_t c) {
-  uint64_t m = (c * 2654435769ull) >> 32;
-  if (m < 1) m = 1;
+  uint64_t m = c / 4 + 1;
   while (gcd_u64(m, c) != 1) ++m;
   return m;
 }

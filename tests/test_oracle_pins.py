@@ -320,7 +320,8 @@ def test_morton_grid_z_curve():
 def test_spread_order_keeps_each_batch_and_steps_across_it(n, S):
     """The spread build (morton = 2) stores each batch of the Morton build in another order: the same points, the
     same batch records, and Eq. 1 words that follow the points; inside a batch of c points the Morton ranks advance
-    by one fixed step coprime with c, about 0.618 c, so that neighbouring positions lie far apart in the batch."""
+    by one fixed step coprime with c, just above c / 4, so that the four points of a quadruple lie in four quarters
+    of the batch while the quadruples' j-th points are Morton neighbours."""
     rng = np.random.default_rng(n)
     xyz = rng.uniform(-20, 20, (n, 3)).astype(np.float32)
     rgba = rng.integers(0, 2**32, n, dtype=np.uint32)
@@ -336,7 +337,11 @@ def test_spread_order_keeps_each_batch_and_steps_across_it(n, S):
         if c > 1:
             steps = np.unique((ranks[1:] - ranks[:-1]) % c)
             assert len(steps) == 1 and math.gcd(int(steps[0]), c) == 1
-            assert abs(int(steps[0]) - 0.6180339887 * c) < 8
+            assert c // 4 < int(steps[0]) <= c // 4 + 8
+            if c % 4 == 0 and int(steps[0]) == c // 4 + 1:  # quadruple q, point j: rank 4q + j * step (mod c)
+                q = np.arange(c // 4)
+                for j in range(4):
+                    assert np.array_equal(ranks[4 * q + j], (4 * q + j * int(steps[0])) % c)
         assert ranks[0] == 0
         src = A.perm[b0 + ranks]
         assert np.array_equal(B.perm[b0:b0 + c], src)
