@@ -43,14 +43,17 @@ def workload(name: str, n_override: int | None):
     if name == "c3":
         n = n_override or 2_000_000_000
         cams = synth.stereo_cameras(synth.C3_SEED)
-        return dict(name="terrain_2e9_stereo_2x2016x2240", seed=synth.C3_SEED, n=n, morton=True, order=0,
-                    cams=cams, desc=f"terrain {n} points, Morton, 10240-point batches, stereo pair "
-                                    f"2x2016x2240, one launch per eye, adaptive precision, culling on")
+        # morton 2 = PR_ORDER_MORTON_SPREAD: the Morton batches, each stored in the spread order
+        return dict(name="terrain_2e9_stereo_2x2016x2240", seed=synth.C3_SEED, n=n, morton=2, order=0,
+                    cams=cams, desc=f"terrain {n} points, Morton-sorted 10240-point batches (each stored in the "
+                                    f"spread order), stereo pair 2x2016x2240, one launch per eye, adaptive "
+                                    f"precision, culling on")
     if name == "c2":
         n = n_override or 100_000_000
         cams = [synth.orbit_camera(f) for f in range(0, 60, 15)]
-        return dict(name="terrain_1e8_orbit_1920x1080", seed=synth.C2_SEED, n=n, morton=True, order=1, cams=cams,
-                    desc=f"terrain {n} points, Morton, orbit frames 0/15/30/45 at 1920x1080")
+        return dict(name="terrain_1e8_orbit_1920x1080", seed=synth.C2_SEED, n=n, morton=2, order=1, cams=cams,
+                    desc=f"terrain {n} points, Morton batches in the spread order, orbit frames 0/15/30/45 at "
+                         f"1920x1080")
     if name == "c1":
         n = n_override or 1_000_000
         return dict(name="primitives_1e6_1280x720", seed=synth.C1_SEED, n=n, morton=False, order=0,
@@ -353,19 +356,19 @@ def multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, plain
     return res
 
 
-def spread_leg(pr, ctx, cloud, cams, vbs, fbs, frame, processed, steps, warmup):
-    """The headline cloud rebuilt in place in the spread order (PR_ORDER_MORTON_SPREAD: the same batches, each
-    stored with a golden-ratio stride over its Morton ranks): the plain step and the multi-view step again."""
+def order_leg(pr, ctx, cloud, cams, vbs, fbs, frame, processed, steps, warmup, order):
+    """The headline cloud rebuilt in place in another point order (PR_ORDER_MORTON: the same Morton batches with
+    their points in plain Morton order): the plain step and the multi-view step again."""
     import numpy as np
     import torch
 
     stream = torch.cuda.current_stream()
     mem, n = cloud["mem"], cloud["n"]
-    # the xyz buffer already holds the Morton order; the colours in that order become the build's input colours
+    # the xyz buffer holds the built order; the colours in that order become the build's input colours
     mem["rgba"][: 4 * n].copy_(mem["colors"][: 4 * n])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pr.pr_build_batches(ctx.handle, cloud["handle"], 10240, pr.PR_ORDER_MORTON_SPREAD)
+    pr.pr_build_batches(ctx.handle, cloud["handle"], 10240, order)
     t_build = time.perf_counter() - t0
     need = pr.pr_views_work_bytes(cloud["handle"], len(cams))
     work = torch.empty(need, dtype=torch.uint8, device="cuda")
@@ -400,7 +403,7 @@ def spread_leg(pr, ctx, cloud, cams, vbs, fbs, frame, processed, steps, warmup):
            "multiview": {"ms_per_step": round(mv, 4), "gpts": round(processed / (mv * 1e-3) / 1e9, 3),
                          "render_views_ms": round(rv, 4)},
            "resolve_ms": round(res_ms, 4)}
-    log(f"spread order: {res}")
+    log(f"order {order}: {res}")
     return res
 
 
@@ -893,8 +896,8 @@ def main():
     ap.add_argument("--array-points", type=int, default=500_000_000,
                     help="points of the 64-camera array leg with the batch-size autotuner (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner leg on the headline workload")
-    ap.add_argument("--no-spread", action="store_true",
-                    help="skip the headline cloud rebuilt in the spread order (PR_ORDER_MORTON_SPREAD)")
+    ap.add_argument("--no-order-leg", action="store_true",
+                    help="skip the headline cloud rebuilt in plain Morton order (PR_ORDER_MORTON) for comparison")
     ap.add_argument("--served-requests", type=int, default=10000)
     ap.add_argument("--served-rates", type=str, default="500,4000",
                     help="offered request rates per second (comma-separated)")
@@ -1011,7 +1014,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["name"], "points": wl["n"], "batches": cloud["nb"], "batch_size": 10240,
                    "views": [f"{c.width}x{c.height}" for c in cams], "precision": "adaptive 10/20/30-bit",
-                   "keys": "u64 depth|index", "description": wl["desc"]},
+                   "keys": "u64 depth|index",
+                   "point_order": {0: "input", 1: "Morton", 2: "Morton batches, spread order inside"}[int(wl["morton"])],
+                   "description": wl["desc"]},
         "processed_points_per_step": processed,
         "all_points_rate_gpts": round(wl["n"] * len(cams) / (ms_per_step * 1e-3) / 1e9, 3),
         "render_kernel_ms": [round(m, 4) for m in mean_render],
@@ -1057,8 +1062,9 @@ def main():
     out["hqs"] = hqs_leg(pr, ctx, cloud, cams, processed, args.steps, args.warmup)
     if not args.no_autotune:
         out["autotune"] = autotune_leg(pr, ctx, cloud, cams, vbs, frame, ms_per_step, args.steps, args.warmup)
-    if not args.no_spread:
-        out["spread_order"] = spread_leg(pr, ctx, cloud, cams, vbs, fbs, frame, processed, args.steps, args.warmup)
+    if not args.no_order_leg and wl["morton"] == pr.PR_ORDER_MORTON_SPREAD:
+        out["plain_morton_order"] = order_leg(pr, ctx, cloud, cams, vbs, fbs, frame, processed, args.steps,
+                                              args.warmup, pr.PR_ORDER_MORTON)
     pr.pr_cloud_free(cloud["handle"])
     cloud["mem"].clear()
     torch.cuda.empty_cache()

@@ -87,14 +87,28 @@ def check_morton_build(ns, tag):
     colors = np.empty(n, np.uint32)
     gb_all = v.batches.cpu().numpy()
 
+    spread = int(ns.wl["morton"]) == 2  # PR_ORDER_MORTON_SPREAD: every batch stored in the spread order
+
     def job(lo):
         hi = min(n, lo + CH)
         perm = _u32(v.perm[lo:hi])
         ox, oc = synth.terrain_gather(seed, n, perm, threads=4)
-        codes = oracle.morton_codes(ox, cmin, cmax)
+        # the Morton order: with the spread order, position r of a batch of c points holds its Morton rank
+        # (r * m) mod c (the oracle's step m), so the ranks are put back first (chunks hold whole batches)
+        mperm, mx = perm, ox
+        if spread:
+            mperm = np.empty_like(perm)
+            mx = np.empty_like(ox)
+            for b0 in range(0, hi - lo, S):
+                c = min(S, hi - lo - b0)
+                rank = (np.arange(c, dtype=np.uint64) * np.uint64(oracle.spread_multiplier(c))) % np.uint64(c)
+                mperm[b0 + rank.astype(np.int64)] = perm[b0:b0 + c]
+                mx[b0 + rank.astype(np.int64)] = ox[b0:b0 + c]
+        codes = oracle.morton_codes(mx, cmin, cmax)
         tie = codes[1:] == codes[:-1]
-        r = dict(lo=lo, mono=bool(np.all(codes[1:] >= codes[:-1])), stable=bool(np.all(perm[1:][tie] > perm[:-1][tie])),
-                 head=(int(codes[0]), int(perm[0])), tail=(int(codes[-1]), int(perm[-1])))
+        r = dict(lo=lo, mono=bool(np.all(codes[1:] >= codes[:-1])),
+                 stable=bool(np.all(mperm[1:][tie] > mperm[:-1][tie])),
+                 head=(int(codes[0]), int(mperm[0])), tail=(int(codes[-1]), int(mperm[-1])))
         r["xyz"] = bool(np.array_equal(_u32(v.xyz[3 * lo:3 * hi]), ox.view(np.uint32).reshape(-1)))
         r["colors"] = bool(np.array_equal(_u32(v.colors[lo:hi]), oc))
         ob = oracle.make_batches(ox, S)

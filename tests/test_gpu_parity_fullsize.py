@@ -98,7 +98,7 @@ def c2(ctx):
     cloud = bench.load_cloud(ctx, wl, on_chunk=keep)
     t0 = _t()
     say("C2: oracle build (Morton sort, batches, Eq. 1) of the same points")
-    B = oracle.build_cloud(seen["xyz"], seen["rgba"], S, morton=True)
+    B = oracle.build_cloud(seen["xyz"], seen["rgba"], S, morton=wl["morton"])
     say(f"C2: oracle build done ({_t() - t0:.1f} s)")
     yield types.SimpleNamespace(wl=wl, cloud=cloud, B=B, n=wl["n"], nb=cloud["nb"])
     import paper_2204_01287_amd as pr
