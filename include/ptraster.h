@@ -177,12 +177,14 @@ enum {
  * splits the 30 bits into low / med / high words.  PR_ORDER_MORTON_SPREAD
  * (an option of this library; the paper fixes no order inside a batch) keeps
  * the same batches but stores a batch of c points so that position r holds
- * its Morton rank (r * m) mod c, m the first integer >= max(1,
- * (c * 2654435769) >> 32) (about 0.618 c) coprime with c: a workgroup's
- * consecutive points then spread over the batch's pixels, which shortens the
- * queues on shared tile entries when many points fall on few pixels (far
- * views, two-view passes), at the cost of a less coherent colour gather in
- * pr_resolve.  perm and colors follow the stored order.  Synchronises the
+ * its Morton rank (r * m) mod c, m the first integer >= floor(c / 4) + 1
+ * coprime with c: the four points a lane loads with one 16-byte word then lie
+ * in four different quarters of the batch, while each of its four point
+ * loops over a wave still walks Morton neighbours.  Back-to-back LDS reads
+ * and atomics of one wave then rarely hit the same tile entries, which
+ * shortens the queues on them (the render and two-view passes are faster;
+ * pr_resolve's colour gather is a little less coherent).  perm and colors
+ * follow the stored order.  Synchronises the
  * stream once.  PR_ENONFINITE if any coordinate is NaN or Inf, PR_EINVAL for
  * an unknown order. */
 pr_status pr_build_batches(pr_ctx* ctx, pr_cloud* cloud, uint32_t batch_size, int morton);

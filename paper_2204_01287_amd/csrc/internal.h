@@ -222,7 +222,7 @@ hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, 
 hipError_t launch_gather(const SortScratch& sc, const float* xyz, const uint32_t* rgba, uint32_t* perm,
                          uint64_t n, uint32_t batch_size, bool spread, float* xyz_out, uint32_t* colors,
                          hipStream_t s);
-// the first integer >= max(1, floor(c * 0.6180339887...)) coprime with c
+// the first integer >= floor(c / 4) + 1 coprime with c
 uint64_t spread_step(uint64_t c);
 hipError_t launch_batch_bbox(const float* xyz, uint64_t n, uint32_t S, uint64_t nb, BatchRec* out, hipStream_t s);
 // variable-size batches: recs[b].first / .count are set, the boxes are filled in

@@ -548,8 +548,7 @@ hipError_t radix_sort_pairs(const SortScratch& sc, uint32_t* vals0, uint64_t n, 
 }
 
 uint64_t spread_step(uint64_t c) {
-  uint64_t m = (c * 2654435769ull) >> 32;  // floor(c * golden fraction), in 32-bit fixed point
-  if (m < 1) m = 1;
+  uint64_t m = c / 4 + 1;
   for (;;) {
     uint64_t a = m, b = c;
     while (b) {
