@@ -627,7 +627,7 @@ def camera_array_leg(pr, ctx, n: int, steps: int, warmup: int, sizes=(5120, 1024
     kept = {}
 
     def build(S):
-        c = _BenchCloud(pr, load_cloud(ctx, dict(name=f"terrain_c4_S{S}", seed=4, n=n, morton=True, order=0,
+        c = _BenchCloud(pr, load_cloud(ctx, dict(name=f"terrain_c4_S{S}", seed=4, n=n, morton=2, order=0,
                                                  batch_size=S)))
         kept[S] = c
         return _Keep(c)
@@ -813,7 +813,7 @@ def served_leg(pr, ctx, nreq: int, rates, budget: int):
     t0 = time.perf_counter()
     clouds = []
     for seed, n in synth.SERVED_CLOUDS:
-        c = load_cloud(ctx, dict(name=f"served_{seed}", seed=seed, n=n, morton=True, order=0))
+        c = load_cloud(ctx, dict(name=f"served_{seed}", seed=seed, n=n, morton=2, order=0))
         pr.pr_cloud_drop_load_buffers(c["handle"])
         pr.pr_sync(ctx.handle)
         for f in ("xyz", "rgba", "perm", "scratch"):

@@ -51,7 +51,7 @@ def c4(ctx):
     import torch
     import bench
 
-    wl = dict(name="terrain_c4", seed=4, n=N, morton=True, order=0, batch_size=10240)
+    wl = dict(name="terrain_c4", seed=4, n=N, morton=2, order=0, batch_size=10240)
     boxes = []
     pool = ThreadPoolExecutor(2)
 
