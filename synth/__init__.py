@@ -51,7 +51,7 @@ def _load():
                                              ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.synth_terrain_gather.restype = ctypes.c_int
         lib.synth_lpc_layout.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
-                                         ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         lib.synth_lpc_layout.restype = ctypes.c_int
@@ -256,9 +256,11 @@ def lpc_depth(n: int, cap: int = 10240) -> int:
     return d
 
 
-def lpc_layout(seed: int, xyz, rgba, depth: int, cap: int = 10240):
+def lpc_layout(seed: int, xyz, rgba, depth: int, cap: int = 10240, spread: bool = True):
     """Layered-point-cloud layout (see synth_lpc_layout): (xyz_out, rgba_out, spans uint32 (nb, 2) = first, count,
-    nodes float64 (nb, 5) = cube origin x, y, z, edge, level).  Padding slots between batches are zero."""
+    nodes float64 (nb, 5) = cube origin x, y, z, edge, level).  Padding slots between batches are zero.  spread: each
+    batch's points in the spread order (slot t holds the batch's point of rank (t * m) mod count in the (level,
+    Morton) order, m the first integer > count / 4 coprime with count), else in that order itself."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float32)
     rgba = np.ascontiguousarray(rgba, dtype=np.uint32)
     n = xyz.shape[0]
@@ -270,7 +272,7 @@ def lpc_layout(seed: int, xyz, rgba, depth: int, cap: int = 10240):
         ro = np.zeros(cap_p, np.uint32)
         spans = np.zeros((cap_b, 2), np.uint32)
         nodes = np.zeros((cap_b, 5), np.float64)
-        rc = _load().synth_lpc_layout(seed, xyz.ctypes.data, rgba.ctypes.data, n, depth, cap, xo.ctypes.data,
+        rc = _load().synth_lpc_layout(seed, xyz.ctypes.data, rgba.ctypes.data, n, depth, cap, int(spread), xo.ctypes.data,
                                       ro.ctypes.data, cap_p, spans.ctypes.data, nodes.ctypes.data, cap_b,
                                       ctypes.byref(npad), ctypes.byref(nb))
         if rc == 0:

@@ -590,14 +590,31 @@ typedef struct {
   const uint32_t* spans;
   float* xyz_out;
   uint32_t* rgba_out;
+  int spread;
 } lpc_gather_job;
+
+/* Spread order of a batch of c points: slot t holds the batch's point of
+ * sorted rank (t * m) mod c, m the first integer >= floor(c / 4) + 1 that is
+ * coprime with c (a bijection of 0..c-1). */
+static uint64_t lpc_spread_step(uint64_t c) {
+  for (uint64_t m = c / 4 + 1;; ++m) {
+    uint64_t a = m, b = c;
+    while (b) {
+      uint64_t r = a % b;
+      a = b;
+      b = r;
+    }
+    if (a == 1) return m;
+  }
+}
 
 static void lpc_gather(void* arg, uint64_t b0, uint64_t b1) {
   lpc_gather_job* G = (lpc_gather_job*)arg;
   for (uint64_t b = b0; b < b1; ++b) {
     uint64_t pos = G->spans[2 * b], cnt = G->spans[2 * b + 1];
+    const uint64_t m = G->spread ? lpc_spread_step(cnt) : 1;
     for (uint64_t t = 0; t < cnt; ++t) {
-      uint64_t s = G->idx[G->src[b] + t], d = pos + t;
+      uint64_t s = G->idx[G->src[b] + (t * m) % cnt], d = pos + t;
       G->xyz_out[3 * d] = G->xyz[3 * s];
       G->xyz_out[3 * d + 1] = G->xyz[3 * s + 1];
       G->xyz_out[3 * d + 2] = G->xyz[3 * s + 2];
@@ -607,8 +624,8 @@ static void lpc_gather(void* arg, uint64_t b0, uint64_t b1) {
 }
 
 int synth_lpc_layout(uint64_t seed, const float* xyz, const uint32_t* rgba, uint64_t n, int depth, uint32_t cap,
-                     float* xyz_out, uint32_t* rgba_out, uint64_t cap_points, uint32_t* spans, double* nodes,
-                     uint64_t cap_batches, uint64_t* npad_out, uint64_t* nb_out) {
+                     int spread, float* xyz_out, uint32_t* rgba_out, uint64_t cap_points, uint32_t* spans,
+                     double* nodes, uint64_t cap_batches, uint64_t* npad_out, uint64_t* nb_out) {
   if (!xyz || !rgba || !npad_out || !nb_out || depth < 0 || depth > 15 || cap < 4 || n >= (1ull << 32)) return -1;
   lpc_keys_job J;
   memset(&J, 0, sizeof J);
@@ -709,7 +726,7 @@ int synth_lpc_layout(uint64_t seed, const float* xyz, const uint32_t* rgba, uint
     i = j;
   }
   if (fits) {
-    lpc_gather_job G = {xyz, rgba, idx, src, spans, xyz_out, rgba_out};
+    lpc_gather_job G = {xyz, rgba, idx, src, spans, xyz_out, rgba_out, spread};
     parallel_for(nb, nt, lpc_gather, &G);
   }
   free(src);

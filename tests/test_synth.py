@@ -101,6 +101,28 @@ def test_lpc_layout_properties():
     assert np.all(pts[1:-1] / pts[:-2] > 3.0) and np.all(pts[1:-1] / pts[:-2] < 5.0)  # about 4x per level
 
 
+def test_lpc_layout_spread_order_permutes_inside_batches():
+    """The layout's default stores each batch in the spread order: the same spans and nodes as the plain (level,
+    Morton) order, and inside a batch of c points slot t holds the plain order's point t * m mod c, for one step m
+    coprime with c just above c / 4."""
+    import math
+
+    xyz, rgba = synth.terrain(7, 100_000, order=1)
+    cap = 1024
+    depth = synth.lpc_depth(len(xyz), cap)
+    xs, rs, spans, nodes = synth.lpc_layout(3, xyz, rgba, depth, cap)
+    xp, rp, spans_p, nodes_p = synth.lpc_layout(3, xyz, rgba, depth, cap, spread=False)
+    assert np.array_equal(spans, spans_p) and np.array_equal(nodes, nodes_p)
+    for f, c in spans[::5]:
+        f, c = int(f), int(c)
+        if c == 1:
+            assert np.array_equal(xs[f], xp[f])
+            continue
+        m = next(k for k in range(c // 4 + 1, c + c // 4 + 2) if math.gcd(k, c) == 1)
+        t = np.arange(c)
+        assert np.array_equal(xs[f:f + c], xp[f + (t * m) % c]) and np.array_equal(rs[f:f + c], rp[f + (t * m) % c])
+
+
 def test_stereo_eyes_share_the_y_and_w_rows():
     """The stereo pairs' eyes differ by a shift along the camera's x axis, so the pixel-space y and w rows of their
     frame matrices (and of every batch's folded matrix) are bit-equal: the two-view pass of the renderer then
