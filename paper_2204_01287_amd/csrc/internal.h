@@ -171,10 +171,14 @@ struct RasterShape {
   // workgroups per CU that fit at once (views = 0: single-view kernel, 1: multi-view kernel)
   int (*per_cu)(int views);
 };
-// The compiled shapes: X(waves, depth, tile).  The first is the default.
+// The compiled shapes: X(waves, depth, tile).  The first is the default: four
+// workgroups of 4 waves fill a CU's 16 wave slots at 128 VGPRs, and a tile of
+// 4992 pixels (39 KiB) is the largest that still lets four of them share the
+// CU's 160 KiB of LDS; the larger tile leaves fewer batches to bands and to
+// the global path than 4096 pixels do.
 #define PR_RASTER_SHAPES(X)                                                                                  \
-  X(4, 5, 4096) X(4, 3, 4096) X(4, 4, 4096) X(4, 6, 4096) X(4, 5, 2048) X(2, 5, 2048) X(2, 5, 4096)        \
-  X(8, 5, 8192) X(1, 5, 1024) X(16, 5, 16384) X(16, 4, 16384) X(8, 5, 16384) X(4, 1, 4096)
+  X(4, 5, 4992) X(4, 3, 4992) X(4, 4, 4992) X(4, 6, 4992) X(4, 5, 2048) X(2, 5, 2048) X(2, 5, 4096)        \
+  X(8, 5, 8192) X(1, 5, 1024) X(16, 5, 16384) X(16, 4, 16384) X(8, 5, 16384) X(4, 1, 4992) X(4, 5, 4096)
 #define PR_SHAPE_NAME_(W_, D_, T_) raster_shape_w##W_##_d##D_##_t##T_
 #define PR_SHAPE_NAME(W_, D_, T_) PR_SHAPE_NAME_(W_, D_, T_)
 #define PR_DECLARE_SHAPE(W_, D_, T_) const RasterShape* PR_SHAPE_NAME_(W_, D_, T_)();

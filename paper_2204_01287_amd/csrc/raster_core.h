@@ -7,7 +7,7 @@
 // one at run time (every shape computes the same result):
 //   PR_WAVES  waves per workgroup (64 lanes each)                  [4]
 //   PR_DEPTH  groups of 256 points in flight per wave (prefetch)   [5]
-//   PR_TILE   pixels of the workgroup's LDS tile (8 bytes each)    [4096]
+//   PR_TILE   pixels of the workgroup's LDS tile (8 bytes each)    [4992]
 #ifndef PR_RASTER_CORE_H
 #define PR_RASTER_CORE_H
 
@@ -20,7 +20,7 @@
 #define PR_DEPTH 5
 #endif
 #ifndef PR_TILE
-#define PR_TILE 4096
+#define PR_TILE 4992
 #endif
 
 namespace ptr {

@@ -64,7 +64,8 @@ def _views(ctx, dc, cams):
 
 def test_shapes(shapes):
     assert len(shapes) >= 2
-    assert (shapes[0]["waves"], shapes[0]["depth"], shapes[0]["tile_px"]) == (4, 5, 4096)
+    assert (shapes[0]["waves"], shapes[0]["depth"], shapes[0]["tile_px"]) == (4, 5, 4992)
+    assert shapes[0]["max_wg_per_cu"] == 4  # the 4992-pixel tile keeps four workgroups per CU
     assert all(s["max_wg_per_cu"] >= 1 for s in shapes)
     assert len({(s["waves"], s["depth"], s["tile_px"]) for s in shapes}) == len(shapes)
 
