@@ -296,6 +296,25 @@ pr_status pr_get_stats(pr_ctx* ctx, pr_stats* out);
 /* Wait for the context's stream; reports device-side failures. */
 pr_status pr_sync(pr_ctx* ctx);
 
+/* Measurement of the render kernel alone (the roofline of Sec. 4.1's
+ * throughput figures needs the kernel's own duration, without the classify
+ * launch and the header reset that pr_render enqueues before it).  With
+ * n > 0 the next n render-kernel launches (the k_render launch of pr_render
+ * and pr_render_hqs, the k_render_views launch of pr_render_views) each
+ * record a pair of HIP events around that launch on the context's stream;
+ * later launches record nothing (a launch enqueued under HIP graph capture
+ * records its pair at every replay of the graph).  Creates the 2n events (host allocations,
+ * never device memory) and drops any earlier ones; n = 0 only drops them.
+ * PR_EINVAL for n > PR_MAX_TIMED_LAUNCHES. */
+#define PR_MAX_TIMED_LAUNCHES 4096
+pr_status pr_time_kernels(pr_ctx* ctx, uint32_t n);
+
+/* Durations of the launches recorded since pr_time_kernels, in ms, in launch
+ * order: ms_out[i] for i < *count (ms_out holds at least capacity floats;
+ * *count = number recorded, at most capacity).  Synchronises on the last
+ * recorded launch. */
+pr_status pr_kernel_times(pr_ctx* ctx, float* ms_out, uint32_t capacity, uint32_t* count);
+
 /* Cloud facts: point count, batch count, batch size (0 before a build). */
 pr_status pr_cloud_info(const pr_cloud* cloud, uint64_t* n, uint64_t* nbatches, uint32_t* batch_size);
 

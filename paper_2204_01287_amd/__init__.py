@@ -18,5 +18,6 @@ from ._binding import (  # noqa: F401
     pr_set_tuning, pr_get_tuning, pr_autotune, pr_stream_probe, pr_render_views_static, PR_STATIC_WORK_BYTES,
     LIB_PATH, lib, pr_last_error, pr_create, pr_destroy, pr_cloud_sizes, pr_load_points, pr_build_batches,
     pr_clear, pr_render, pr_resolve, pr_get_stats, pr_sync, pr_cloud_info, pr_cloud_free, EXPORTED,
+    pr_time_kernels, pr_kernel_times, PR_MAX_TIMED_LAUNCHES,
     DeviceCloud, Context,
 )

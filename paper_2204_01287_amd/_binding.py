@@ -35,7 +35,7 @@ EXPORTED = ["pr_last_error", "pr_create", "pr_destroy", "pr_cloud_sizes", "pr_lo
             "pr_clear", "pr_render", "pr_resolve", "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_cloud_free",
             "pr_views_work_bytes", "pr_render_views", "pr_cloud_drop_load_buffers", "pr_render_hqs",
             "pr_cloud_sizes_spans", "pr_build_batches_spans", "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning",
-            "pr_autotune", "pr_stream_probe", "pr_render_views_static"]
+            "pr_autotune", "pr_stream_probe", "pr_render_views_static", "pr_time_kernels", "pr_kernel_times"]
 
 
 class PrError(RuntimeError):
@@ -135,12 +135,15 @@ lib.pr_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
 lib.pr_autotune.argtypes = [_P, _P, ctypes.POINTER(View), _U32, ctypes.POINTER(RenderOpts), _P, _U64, _U32,
                             ctypes.POINTER(TuneTrial), _U32, ctypes.POINTER(_U32), ctypes.POINTER(Tuning)]
 lib.pr_cloud_info.argtypes = [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U32)]
+lib.pr_time_kernels.argtypes = [_P, _U32]
+lib.pr_kernel_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float), _U32, ctypes.POINTER(_U32)]
 lib.pr_cloud_free.argtypes = [_P]
 lib.pr_cloud_free.restype = None
 for _f in ("pr_create", "pr_cloud_sizes", "pr_load_points", "pr_build_batches", "pr_clear", "pr_render", "pr_resolve",
            "pr_get_stats", "pr_sync", "pr_cloud_info", "pr_views_work_bytes", "pr_render_views",
            "pr_cloud_drop_load_buffers", "pr_render_hqs", "pr_cloud_sizes_spans", "pr_build_batches_spans",
-           "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning", "pr_autotune", "pr_stream_probe"):
+           "pr_raster_shapes", "pr_set_tuning", "pr_get_tuning", "pr_autotune", "pr_stream_probe",
+           "pr_time_kernels", "pr_kernel_times"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -333,6 +336,22 @@ def pr_get_stats(ctx) -> dict:
 
 def pr_sync(ctx):
     _check(lib.pr_sync(ctx), "pr_sync")
+
+
+PR_MAX_TIMED_LAUNCHES = 4096
+
+
+def pr_time_kernels(ctx, n: int):
+    """Arm event pairs around the next n render-kernel launches of the context (0: off)."""
+    _check(lib.pr_time_kernels(ctx, int(n)), "pr_time_kernels")
+
+
+def pr_kernel_times(ctx, capacity: int = PR_MAX_TIMED_LAUNCHES) -> list:
+    """Durations (ms) of the render-kernel launches recorded since pr_time_kernels, in launch order."""
+    buf = (ctypes.c_float * max(int(capacity), 1))()
+    cnt = _U32()
+    _check(lib.pr_kernel_times(ctx, buf, int(capacity), ctypes.byref(cnt)), "pr_kernel_times")
+    return [float(buf[i]) for i in range(cnt.value)]
 
 
 def pr_cloud_info(cloud):

@@ -43,6 +43,8 @@ struct pr_ctx {
   uint32_t per_cu[kNumShapes][2];   // workgroups per CU that fit at once: single-view, multi-view kernel
   uint32_t accum_grid;              // persistent workgroups of the shading pass
   pr_tuning tuning;                 // render shape, tile bound and grid of this context's frames
+  std::vector<hipEvent_t> tev;      // pr_time_kernels: 2 events per armed render launch
+  uint32_t t_used = 0;              // launches recorded so far
 };
 
 struct pr_cloud {
@@ -165,6 +167,25 @@ pr_status sizes_spans(uint64_t n, uint64_t nb, pr_sizes* s) {
   return PR_OK;
 }
 
+// The event pair of the next render launch, if pr_time_kernels armed one (else nullptr).
+hipEvent_t* timed_pair(pr_ctx* ctx) {
+  return 2u * ctx->t_used < ctx->tev.size() ? &ctx->tev[2u * ctx->t_used] : nullptr;
+}
+
+// A render launch between its timing events (when armed).
+template <typename Launch>
+hipError_t timed_launch(pr_ctx* ctx, Launch&& launch) {
+  hipEvent_t* ev = timed_pair(ctx);
+  if (ev) {
+    const hipError_t e = hipEventRecord(ev[0], ctx->stream);
+    if (e != hipSuccess) return e;
+  }
+  const hipError_t e = launch();
+  if (e != hipSuccess || !ev) return e;
+  ctx->t_used++;
+  return hipEventRecord(ev[1], ctx->stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -220,6 +241,7 @@ void pr_destroy(pr_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
   (void)hipFree(ctx->dev);
   delete ctx;
 }
@@ -459,7 +481,7 @@ pr_status render_frame(pr_ctx* ctx, const pr_cloud* cloud, const float view[16],
   a.nodes = cloud->lod ? static_cast<const ptr::LodNode*>(cloud->bufs.nodes) : nullptr;
   a.lod_px = o.lod_px;
   HIP_TRY(ptr::launch_classify(a, ctx->stream), "classify");
-  HIP_TRY(shape_of(tune).render(a, ctx->stream), "render");
+  HIP_TRY(timed_launch(ctx, [&] { return shape_of(tune).render(a, ctx->stream); }), "render");
   return PR_OK;
 }
 
@@ -604,7 +626,8 @@ pr_status render_views(pr_ctx* ctx, const pr_cloud* cloud, const pr_view* views,
   r.grid = shape_grid(ctx, tune, 1);
   r.cap = (uint32_t)(nb * nchunks);
   for (uint32_t v = 0; v < nviews; ++v) r.v[v] = {views[v].visbuf, views[v].w, views[v].h};
-  HIP_TRY(shape_of(tune).render_views(r, nb * nchunks, o.counters ? 1 : 0, ctx->stream), "render views");
+  HIP_TRY(timed_launch(ctx, [&] { return shape_of(tune).render_views(r, nb * nchunks, o.counters ? 1 : 0, ctx->stream); }),
+          "render views");
   return PR_OK;
 }
 
@@ -681,6 +704,40 @@ pr_status pr_sync(pr_ctx* ctx) {
   if (pr_status s = set_device(ctx)) return s;
   HIP_TRY(hipStreamSynchronize(ctx->stream), "pr_sync");
   HIP_TRY(hipGetLastError(), "pr_sync");
+  return PR_OK;
+}
+
+pr_status pr_time_kernels(pr_ctx* ctx, uint32_t n) {
+  if (!ctx) return fail(PR_EINVAL, "pr_time_kernels: NULL context");
+  if (n > PR_MAX_TIMED_LAUNCHES)
+    return fail(PR_EINVAL, "pr_time_kernels: %u launches above the maximum of %u", n, PR_MAX_TIMED_LAUNCHES);
+  if (pr_status s = set_device(ctx)) return s;
+  // events still pending on the stream are not destroyed under it
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "pr_time_kernels");
+  for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
+  ctx->tev.clear();
+  ctx->t_used = 0;
+  for (uint32_t i = 0; i < 2 * n; ++i) {
+    hipEvent_t e;
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      for (hipEvent_t d : ctx->tev) (void)hipEventDestroy(d);
+      ctx->tev.clear();
+      return hip_fail(r, "pr_time_kernels: hipEventCreate");
+    }
+    ctx->tev.push_back(e);
+  }
+  return PR_OK;
+}
+
+pr_status pr_kernel_times(pr_ctx* ctx, float* ms_out, uint32_t capacity, uint32_t* count) {
+  if (!ctx || !count || (capacity && !ms_out)) return fail(PR_EINVAL, "pr_kernel_times: NULL argument");
+  if (pr_status s = set_device(ctx)) return s;
+  const uint32_t m = ctx->t_used < capacity ? ctx->t_used : capacity;
+  if (m) HIP_TRY(hipEventSynchronize(ctx->tev[2 * (m - 1) + 1]), "pr_kernel_times: hipEventSynchronize");
+  for (uint32_t i = 0; i < m; ++i)
+    HIP_TRY(hipEventElapsedTime(&ms_out[i], ctx->tev[2 * i], ctx->tev[2 * i + 1]), "pr_kernel_times: hipEventElapsedTime");
+  *count = m;
   return PR_OK;
 }
 

@@ -306,3 +306,41 @@ def test_clear_and_accumulate(ctx, c1):
     pr.pr_sync(ctx.handle)
     ref_b, _ = oracle.render(B, other.view, other.proj, w, h)
     assert_vb_equal(vb.cpu().numpy().view(np.uint64), np.minimum(ref_a, ref_b), w)
+
+
+def test_kernel_timing_events(ctx, c1):
+    """pr_time_kernels: the armed render launches (plain and multi-view) each time their kernel, the frames stay
+    bit-equal to the oracle, later launches are not recorded, 0 disarms, and too many launches are refused."""
+    import torch
+    import paper_2204_01287_amd as pr
+
+    dc, B = c1
+    cam = synth.c1_camera()
+    other = synth.random_camera(np.random.default_rng(21), cam.width, cam.height)
+    w, h = cam.width, cam.height
+    ref_a, _ = oracle.render(B, cam.view, cam.proj, w, h)
+    ref_b, _ = oracle.render(B, other.view, other.proj, w, h)
+    vb = torch.empty(w * h, dtype=torch.int64, device="cuda")
+    vb2 = torch.empty(w * h, dtype=torch.int64, device="cuda")
+    say("kernel timing: 3 armed launches, 4 made")
+    pr.pr_time_kernels(ctx.handle, 3)
+    assert pr.pr_kernel_times(ctx.handle) == []
+    pr.pr_render(ctx.handle, dc.handle, cam.view, cam.proj, w, h, None, vb)
+    need = pr.pr_views_work_bytes(dc.handle, 2)
+    work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    views = [(cam.view, cam.proj, w, h, vb), (other.view, other.proj, w, h, vb2)]
+    pr.pr_render_views(ctx.handle, dc.handle, views, None, work, need)
+    pr.pr_render(ctx.handle, dc.handle, other.view, other.proj, w, h, None, vb2)
+    pr.pr_render(ctx.handle, dc.handle, cam.view, cam.proj, w, h, None, vb)
+    t = pr.pr_kernel_times(ctx.handle)
+    assert len(t) == 3 and all(0.0 < x < 1000.0 for x in t), t
+    assert pr.pr_kernel_times(ctx.handle, 2) == t[:2]
+    assert_vb_equal(vb.cpu().numpy().view(np.uint64), ref_a, w)
+    assert_vb_equal(vb2.cpu().numpy().view(np.uint64), ref_b, w)
+    pr.pr_time_kernels(ctx.handle, 0)
+    pr.pr_render(ctx.handle, dc.handle, cam.view, cam.proj, w, h, None, vb)
+    assert pr.pr_kernel_times(ctx.handle) == []
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_time_kernels(ctx.handle, pr.PR_MAX_TIMED_LAUNCHES + 1)
+    assert e.value.name == "PR_EINVAL"
+    pr.pr_sync(ctx.handle)
