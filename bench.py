@@ -332,10 +332,21 @@ def multiview_and_graphs(pr, ctx, cloud, cams, vbs, fbs, frame, processed, plain
     pr.pr_render_views(ctx.handle, cloud["handle"], vlist, pr.RenderOpts.make(counters=1), work, need)
     st = pr.pr_get_stats(ctx.handle)
     rv_ms = timed_ms(lambda: pr.pr_render_views(ctx.handle, cloud["handle"], vlist, None, work, need), steps, warmup)
+    # the render kernel alone: the library's event pair around its launch
+    pr.pr_time_kernels(ctx.handle, steps)
+    for _ in range(steps):
+        pr.pr_render_views(ctx.handle, cloud["handle"], vlist, None, work, need)
+    torch.cuda.synchronize()
+    kv_ms = float(np.mean(pr.pr_kernel_times(ctx.handle)))
+    pr.pr_time_kernels(ctx.handle, 0)
+    words_note = ("coordinate words streamed once per batch at the highest level among its live views + 80 B per "
+                  "live (batch, view) record")
     res = {"launches": "one clear, one classify, one render launch for both eyes; resolve per eye",
            "roofline": roofline(render_bytes(st), rv_ms, "pr_render_views (clear, classify, render of both eyes)",
-                                "coordinate words streamed once per batch at the highest level among its live "
-                                "views + 80 B per live (batch, view) record"),
+                                words_note),
+           "roofline_kernel": roofline(render_bytes(st), kv_ms, "k_render_views (the render launch of "
+                                       "pr_render_views, timed by HIP events around it: pr_time_kernels)",
+                                       words_note),
            "ms_per_step": round(float(np.mean(mv)), 4),
            "gpts": round(processed / (float(np.mean(mv)) * 1e-3) / 1e9, 3),
            "frame_ms_p50": round(float(np.percentile(mv, 50)), 4),
