@@ -562,16 +562,30 @@ __device__ __forceinline__ void raster_by_class(int cls, const Loop& L, const St
 // pixel once into the global buffer, leaving the entry PR_EMPTY for the next
 // batch.  Most covered pixels improve the global minimum, so the atomic is
 // issued without a prior read (no round trip on this path).
+// The entry's row and column are stepped with the loop instead of divided
+// out per entry: floor((tid + 1/2) * rcp(tw)) is exactly floor(tid / tw) in
+// binary32 (the reciprocal within an ulp moves the product by less than the
+// distance 1/(2 tw) of the half-integer numerator's quotient to an integer,
+// for numerators below 2^20), and one carry per step keeps lx below tw.
 __device__ __forceinline__ void flush_tile(uint64_t* tile, uint32_t tid, uint64_t* vb, uint32_t W, uint32_t x0,
                                            uint32_t y0, uint32_t tw, uint32_t th, uint32_t& natom) {
   const uint32_t n = tw * th;
+  const float rtw = __builtin_amdgcn_rcpf((float)tw);
+  const uint32_t dy = (uint32_t)(((float)THREADS + 0.5f) * rtw), dx = THREADS - dy * tw;
+  uint32_t ly = (uint32_t)(((float)tid + 0.5f) * rtw), lx = tid - ly * tw;
+  uint64_t* const base = vb + ((uint64_t)y0 * W + x0);
   for (uint32_t e = tid; e < n; e += THREADS) {
     const uint64_t v = tile[e];
     if (v != ~0ull) {
       tile[e] = ~0ull;
-      const uint32_t ly = e / tw, lx = e - ly * tw;
-      __hip_atomic_fetch_min(vb + ((y0 + ly) * W + (x0 + lx)), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_min(base + (__umul24(ly, W) + lx), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       natom++;
+    }
+    lx += dx;
+    ly += dy;
+    if (lx >= tw) {
+      lx -= tw;
+      ly += 1u;
     }
   }
 }
@@ -744,12 +758,16 @@ __device__ __forceinline__ void render_pair(const LiveBatch& ra, const ViewOut& 
 // nb - 2, ...).  Queue position p of n = nt + nd takes an untiled one iff
 // floor((p + 1) nd / n) > floor(p nd / n), which spreads the untiled batches
 // (and their global atomics) evenly over the frame.  Returns ~0u past the end.
+// One division: with k = floor(p nd / n) and r = p nd - k n, the next
+// quotient is k + floor((r + nd) / n), and r + nd < 2n, so it exceeds k iff
+// r >= n - nd = nt.
 __device__ __forceinline__ uint32_t live_slot(uint32_t p, uint32_t nt, uint32_t nd, uint32_t nb) {
   const uint32_t n = nt + nd;
   if (p >= n) return ~0u;
   if (nd == 0) return p;
-  const uint32_t k = (uint32_t)(((uint64_t)p * nd) / n), k1 = (uint32_t)(((uint64_t)(p + 1) * nd) / n);
-  return k1 > k ? nb - 1u - k : p - k;
+  const uint64_t num = (uint64_t)p * nd;
+  const uint32_t k = (uint32_t)(num / n), r = (uint32_t)(num - (uint64_t)k * n);
+  return r >= nt ? nb - 1u - k : p - k;
 }
 
 __device__ __forceinline__ void fill_tile(uint64_t* tile, uint32_t tid) {
