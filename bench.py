@@ -219,6 +219,27 @@ def cpu_baseline(wl, sample_n: int, seconds: float):
                                "seconds": round(secs1, 2)})
 
 
+def cpu_single_c1(seconds: float = 1.0) -> dict:
+    """The oracle on one thread over the C1 workload (the 8 primitives, 1e6 points, 1280x720): its frame time, as the
+    host's reference for the small configuration."""
+    import oracle
+    import synth
+
+    wl = workload("c1", None)
+    xyz, rgba = synth.primitives(wl["seed"], wl["n"])
+    B = oracle.build_cloud(xyz, rgba, 10240, morton=wl["morton"])
+    cam = wl["cams"][0]
+    pts, secs, frames = 0, 0.0, 0
+    while secs < seconds or frames < 3:
+        t = time.perf_counter()
+        _, st = oracle.render(B, cam.view, cam.proj, cam.width, cam.height)
+        secs += time.perf_counter() - t
+        pts += st["points"]
+        frames += 1
+    return {"workload": wl["name"], "ms_per_frame": round(secs / frames * 1e3, 3),
+            "value": round(pts / secs / 1e9, 6), "unit": "Gpoints/s", "frames": frames, "threads": 1}
+
+
 def profile_counters(kernel_src_hash: str, workload_name: str) -> dict:
     """Counters of the render kernel (HBM bytes, VALU instructions per launch) from the committed rocprofv3 --pmc
     summary, if it was taken on these kernel sources; else {}."""
@@ -1102,6 +1123,7 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl["n"]), args.cpu_seconds)
+        out["cpu_baseline"]["single_thread_c1"] = cpu_single_c1()
     print(json.dumps(out), flush=True)
     ctx.close()
 
